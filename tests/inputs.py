@@ -1,0 +1,67 @@
+"""Seeded synthetic inputs shared by the GPU tests and the oracle tests.
+
+Nothing here computes any part of the method: it only draws random +1/-1
+matrices with the structure the method assumes (column 0 all +1, every
+other column balanced) and converts between the two storage layouts:
+
+* unpacked: int8 [n][m][m], entry [k, i, j] = row i, column j of matrix k;
+* packed:   uint32 [n][m][W], W = ceil(m / 32); bit (r % 32) of word r // 32
+  of column j is 1 iff entry (r, j) is -1; unused high bits are 0.
+"""
+import numpy as np
+
+
+def words(m: int) -> int:
+    return (m + 31) // 32
+
+
+def random_population(m: int, n: int, seed: int) -> np.ndarray:
+    """n matrices: column 0 all +1, other columns uniformly random balanced."""
+    rng = np.random.default_rng(seed)
+    base = np.where(np.arange(m) < m // 2, -1, 1).astype(np.int8)
+    cols = np.tile(base, (n, m - 1, 1))            # [n][m-1][m]
+    idx = rng.random((n, m - 1, m)).argsort(axis=2)
+    cols = np.take_along_axis(cols, idx, axis=2)
+    pop = np.ones((n, m, m), dtype=np.int8)
+    pop[:, :, 1:] = cols.transpose(0, 2, 1)
+    return np.ascontiguousarray(pop)
+
+
+def pack(pop: np.ndarray) -> np.ndarray:
+    pop = np.asarray(pop)
+    n, m, _ = pop.shape
+    W = words(m)
+    bits = (pop == -1).astype(np.uint64)          # [n][row][col]
+    out = np.zeros((n, m, W), dtype=np.uint32)
+    for w in range(W):
+        rows = range(32 * w, min(m, 32 * w + 32))
+        acc = np.zeros((n, m), dtype=np.uint64)
+        for r in rows:
+            acc |= bits[:, r, :] << np.uint64(r - 32 * w)
+        out[:, :, w] = acc.astype(np.uint32)
+    return out
+
+
+def unpack(packed: np.ndarray, m: int) -> np.ndarray:
+    packed = np.asarray(packed, dtype=np.uint32)
+    n = packed.shape[0]
+    W = words(m)
+    packed = packed.reshape(n, m, W)
+    pop = np.ones((n, m, m), dtype=np.int8)
+    for r in range(m):
+        bit = (packed[:, :, r // 32] >> np.uint32(r % 32)) & np.uint32(1)   # [n][col]
+        pop[:, r, :] = np.where(bit == 1, -1, 1)
+    return pop
+
+
+def all_m4_normalized() -> np.ndarray:
+    """All 6^3 = 216 normalized 4x4 matrices with balanced columns 1..3."""
+    import itertools
+    balanced = [np.array(v, dtype=np.int8) for v in itertools.product([1, -1], repeat=4)
+                if sum(v) == 0]
+    out = []
+    for c1, c2, c3 in itertools.product(balanced, repeat=3):
+        Q = np.ones((4, 4), dtype=np.int8)
+        Q[:, 1], Q[:, 2], Q[:, 3] = c1, c2, c3
+        out.append(Q)
+    return np.stack(out)
