@@ -1,0 +1,291 @@
+#!/usr/bin/env python
+"""Benchmark of the GA hot path on one MI355X.
+
+Default workload (one "step" = one whole run of the plain GA: init,
+fitness, 500 generations): order m = 20, population n = 40,000, seed 1,
+fitness SQ (and, timed beside it, ABS), binary tournament, crossover 0.5,
+one pair flip per child at rate 0.1, stop-on-found off.  Prints one JSON
+line with the throughput in evaluations per second (n fitness evaluations
+per generation plus the initial population), the roofline of the fused
+children kernel, the oracle's CPU throughput and the time-to-solve of the
+m = 8, n = 1,024 plain GA over 32 seeds.
+
+--workload batched: 24 runs in one batched launch per generation against
+the same 24 runs one after another.
+--workload served: a Poisson stream of search requests through the server.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz of 32-bit integer vector ALU issue
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def ops_per_eval(m: int, kind: int) -> int:
+    """Integer ALU ops of the packed Gram + fitness of one individual:
+    per column pair (i < j, columns 1..m-1) one xor and one popcount per
+    word plus the key's accumulation (SQ: one multiply-add of the centred
+    count; ABS: one absolute-difference add; NNZ: compare + add)."""
+    import paper_2208_14961_amd as ga
+    w = (m + 31) // 32
+    pairs = (m - 1) * (m - 2) // 2
+    acc = {ga.FIT_SQ: 1, ga.FIT_ABS: 1, ga.FIT_F1: 1, ga.FIT_NNZ: 2, ga.FIT_F2: 2,
+           ga.FIT_SQ_PLUS_NNZ: 3}[kind]
+    return pairs * (2 * w + acc)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def buffers(cfg):
+    import torch
+    import paper_2208_14961_amd as ga
+    sh = ga.pop_shape(cfg)
+    pa = torch.zeros(sh, dtype=torch.int32, device="cuda")
+    pb = torch.zeros_like(pa)
+    ka = torch.zeros((cfg.n,), dtype=torch.int32, device="cuda")
+    kb = torch.zeros_like(ka)
+    return pa, pb, ka, kb
+
+
+def timed_runs(cfg, bufs, steps):
+    import torch
+    import paper_2208_14961_amd as ga
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ga.ga_run(cfg, *bufs)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(m, n, seed, kind, budget_s=15.0):
+    """The oracle (plain C, OpenMP over individuals) on a bounded sample of
+    the same workload: init, fitness and as many generations as fit in about
+    budget_s seconds."""
+    from oracle import gao
+    probe = gao.Config(m=m, n=n, seed=seed, fitness=kind, max_generations=2,
+                       stop_on_found=False)
+    t = time.perf_counter()
+    gao.run(probe)
+    per_gen = (time.perf_counter() - t) / 3
+    gens = max(2, min(500, int(budget_s / max(per_gen, 1e-6)) - 1))
+    cfg = gao.Config(m=m, n=n, seed=seed, fitness=kind, max_generations=gens,
+                     stop_on_found=False)
+    t = time.perf_counter()
+    gao.run(cfg)
+    dt = time.perf_counter() - t
+    return {"value": n * (gens + 1) / dt, "unit": "evals/s", "cores": gao.num_threads(),
+            "kind": "oracle",
+            "sample": f"m={m}, n={n}, seed {seed}: init + fitness + {gens} generations "
+                      f"({dt:.1f} s)"}
+
+
+def time_to_solve(runs=32):
+    """Plain GA, m=8, n=1,024, 200-generation budget, stop at key 0: wall
+    time of each whole run (synchronous ga_run) over seeds 0..runs-1."""
+    import paper_2208_14961_amd as ga
+    times, gens, solved = [], [], 0
+    cfg0 = ga.Config(m=8, n=1024, max_generations=200)
+    bufs = buffers(cfg0)
+    ga.ga_run(cfg0, *bufs)  # warm
+    for s in range(runs):
+        cfg = ga.Config(m=8, n=1024, seed=s, max_generations=200)
+        t = time.perf_counter()
+        r = ga.ga_run(cfg, *bufs)
+        times.append(time.perf_counter() - t)
+        if r["found"]:
+            solved += 1
+            gens.append(r["generation"])
+    return {"workload": "plain GA m=8 n=1024, seeds 0..%d, budget 200" % (runs - 1),
+            "runs": runs, "solved": solved,
+            "p50_ms": 1e3 * percentile(times, 50), "p99_ms": 1e3 * percentile(times, 99),
+            "mean_generations": (sum(gens) / len(gens)) if gens else None}
+
+
+def bench_default(args):
+    import torch
+    import paper_2208_14961_amd as ga
+    G, n, m = 500, 40000, 20
+    cfg = ga.Config(m=m, n=n, seed=1, fitness=ga.FIT_SQ, max_generations=G, flags=0)
+    cfg_abs = ga.Config(m=m, n=n, seed=1, fitness=ga.FIT_ABS, max_generations=G, flags=0)
+    bufs = buffers(cfg)
+    for _ in range(args.warmup):
+        ga.ga_run(cfg, *bufs)
+        ga.ga_run(cfg_abs, *bufs)
+    dt = timed_runs(cfg, bufs, args.steps)
+    dt_abs = timed_runs(cfg_abs, bufs, args.steps)
+    evals = n * (G + 1)
+    # roofline of the fused children kernel: one more run with each launch
+    # bracketed by HIP events on the library's stream
+    ga.ga_timing_enable(True)
+    ga.ga_run(cfg, *bufs)
+    mean_ms, launches = ga.ga_timing_read()
+    ga.ga_timing_enable(False)
+    achieved = n * ops_per_eval(m, ga.FIT_SQ) / (mean_ms * 1e-3) / 1e12
+    out = {
+        "metric": "Gram+fitness evals/s and generations/s at m=20,pop=40k; p50/p99 time-to-solve",
+        "value": args.steps * evals / dt,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "plain GA, m=20, n=40000, seed 1, fitness SQ, 500 generations, "
+                               "tournament 2, crossover 0.5, pair-flip 0.1, stop-on-found off",
+                   "m": m, "n": n, "generations": G},
+        "generations_per_s": args.steps * G / dt,
+        "abs_keyed": {"value": args.steps * evals / dt_abs, "unit": "evals/s",
+                      "generations_per_s": args.steps * G / dt_abs},
+        "roofline": {"bound": "alu", "kernel": "children_one_kernel<20>",
+                     "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                     "mean_launch_ms": mean_ms, "launches": launches,
+                     "ops_per_eval": ops_per_eval(m, ga.FIT_SQ)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(m, n, 1, ga.FIT_SQ, budget_s=args.cpu_seconds)
+    out["time_to_solve"] = time_to_solve()
+    return out
+
+
+def workload_batched(meta_seed=4, count=24):
+    """24 runs: orders from {12,16,20,24,28,36}, sizes uniform in
+    [2000, 60000], seeds meta_seed*10^6 + i, 300 generations each."""
+    import numpy as np
+    import paper_2208_14961_amd as ga
+    rng = np.random.default_rng(meta_seed)
+    cfgs = []
+    for i in range(count):
+        m = int(rng.choice([12, 16, 20, 24, 28, 36]))
+        n = int(rng.integers(2000, 60001))
+        cfgs.append(ga.Config(m=m, n=n, seed=meta_seed * 10**6 + i, max_generations=300,
+                              flags=0))
+    return cfgs
+
+
+def bench_batched(args):
+    import torch
+    import paper_2208_14961_amd as ga
+    cfgs = workload_batched()
+    gens = sum(c.max_generations for c in cfgs)
+    evals = sum(c.n * (c.max_generations + 1) for c in cfgs)
+    ga.ga_run_batch(cfgs[:2])  # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        ga.ga_run_batch(cfgs)
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t) / args.steps
+    t = time.perf_counter()
+    for c in cfgs:
+        ga.ga_run(c, *buffers(c))
+    torch.cuda.synchronize()
+    dt_p = time.perf_counter() - t
+    return {
+        "metric": "batched generations/s (24 runs) vs one run per launch",
+        "value": gens / dt_b, "unit": "generations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": 1e3 * dt_b, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "batched: 24 runs, m in {12..36}, n in [2000,60000], 300 gens"},
+        "evals_per_s": evals / dt_b,
+        "plain": {"generations_per_s": gens / dt_p, "evals_per_s": evals / dt_p,
+                  "seconds": dt_p},
+        "speedup_vs_plain": dt_p / dt_b,
+    }
+
+
+def workload_served(meta_seed=5, count=2000, rate=50.0):
+    """Poisson arrivals (mean `rate`/s); order uniform over multiples of 4 in
+    [8, 64]; size uniform in [1000, 50000]; 2000-generation budget."""
+    import numpy as np
+    import paper_2208_14961_amd as ga
+    rng = np.random.default_rng(meta_seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    arr = np.cumsum(gaps) - gaps[0]
+    cfgs = []
+    for i in range(count):
+        m = int(4 * rng.integers(2, 17))
+        n = int(rng.integers(1000, 50001))
+        cfgs.append(ga.Config(m=m, n=n, seed=meta_seed * 10**6 + i, max_generations=2000))
+    return cfgs, arr
+
+
+def bench_served(args):
+    import paper_2208_14961_amd as ga
+    count = args.requests
+    cfgs, arrivals = workload_served(count=count)
+    srv = ga.Server(hbm_budget_bytes=200 * 10**9)
+    t0 = time.perf_counter()
+    ids = []
+    for c, a in zip(cfgs, arrivals):
+        now = time.perf_counter() - t0
+        if a > now:
+            time.sleep(a - now)
+        ids.append(srv.submit(c))
+    results = [srv.wait(i) for i in ids]
+    wall = time.perf_counter() - t0
+    lat = [srv.latency(i) for i in ids]
+    srv.close()
+    solved = [l for l, r in zip(lat, results) if r["found"]]
+    evals = sum(c.n * (r["generation"] + 1) for c, r in zip(cfgs, results))
+    return {
+        "metric": "served search: requests/s and p50/p99 time-to-first-Hadamard",
+        "value": count / wall, "unit": "requests/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * wall, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"served: {count} Poisson requests at 50/s, m in 8..64 step 4, "
+                               "n in [1000,50000], budget 2000 generations, 200 GB admission"},
+        "evals_per_s": evals / wall,
+        "solved": len(solved), "requests": count,
+        "time_to_first_hadamard": {"p50_s": percentile(solved, 50),
+                                   "p99_s": percentile(solved, 99)},
+        "time_to_retire": {"p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99)},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="default", choices=["default", "batched", "served"])
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(independent runs would shard by run; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    fn = {"default": bench_default, "batched": bench_batched, "served": bench_served}
+    out = fn[args.workload](args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,243 @@
+/*
+ * ga.h -- C ABI of libga, the MI355X (gfx950) implementation of the
+ * per-generation hot path of the genetic algorithm for Hadamard matrices of
+ * Balogh & Ruiz ("A GPU accelerated Genetic Algorithm for the Construction
+ * of Hadamard Matrices", arXiv 2208.14961).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Population layout ("packed").  A population of n matrices of order m is an
+ * array of uint32 words pop[n][m][W], W = ceil(m / 32).  Column j of matrix
+ * k occupies words pop[k][j][0..W-1]; bit (r % 32) of word r / 32 is 1 iff
+ * entry (row r, column j) is -1.  Bits for rows >= m are 0.  The paper
+ * stores int8 entries Q[m*m*k + m*i + j] (Sec. 3.4); this layout holds the
+ * same matrices with one bit per entry, so that the dot product of two
+ * columns is c_i . c_j = m - 2 * popcount(x_i xor x_j).
+ *
+ * Invariants (Sec. 3.1).  Column 0 of every matrix is all +1 (its words are
+ * 0) and every other column is balanced (m/2 entries -1).  Initialization,
+ * crossover (whole columns, Sec. 3.4) and mutation (flips of unequal entry
+ * pairs only, Sec. 3.5) keep them.  The fitness kernels rely on them: pairs
+ * involving column 0 are orthogonal and are skipped.
+ *
+ * Keys.  Each individual's fitness key is a uint32, smaller is fitter, and 0
+ * exactly for Hadamard matrices.  With G = Q^T Q and pairs i < j of columns:
+ *   GA_FIT_SQ            sum G_ij^2
+ *   GA_FIT_ABS           sum |G_ij|              (= F1 / 2)
+ *   GA_FIT_NNZ           #{G_ij != 0}            (= F2 / 2)
+ *   GA_FIT_SQ_PLUS_NNZ   SQ + NNZ
+ *   GA_FIT_F1            sum_{i,j} |G_ij| - m^2  (Sec. 3.2, Eq. fitness0)
+ *   GA_FIT_F2            nnz(G) - m              (Sec. 3.2, Eq. fitness)
+ * Components (optional) are the triple (SQ, ABS, NNZ) per individual.
+ *
+ * Randomness.  Every random choice is word d % 4 of the Philox4x32-10 block
+ * (Salmon et al., SC'11) with counter (d / 4, index, generation, stream) and
+ * key (seed low 32 bits, seed high 32 bits).  Streams: 1 initialization,
+ * 2 selection, 3 crossover (and the per-child mutation coin), 4 mutation,
+ * 5 parent permutation.  Bounded integers are floor(u * range / 2^32);
+ * a coin with threshold t (0 <= t <= 2^32) succeeds iff u < t.
+ *
+ * Device pointers and streams.  Unless stated otherwise, pointer arguments
+ * are device pointers owned by the caller, and `stream` is a hipStream_t
+ * (NULL = the null stream).  Calls marked "async" only enqueue work.
+ *
+ * Errors.  No call aborts or throws.  Each returns a ga_status; on error
+ * ga_last_error() gives a message for the calling thread.
+ */
+#ifndef GA_H
+#define GA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GA_OK = 0,
+  GA_PENDING = 1,     /* ga_poll: the request has not finished yet          */
+  GA_EINVAL = -1,     /* invalid configuration or argument                   */
+  GA_ENOMEM = -2,     /* device allocation failed                            */
+  GA_EDEVICE = -3,    /* a HIP call failed; see ga_last_error()              */
+  GA_EBUDGET = -4,    /* a request can never fit the server's HBM budget     */
+  GA_ENOTFOUND = -5   /* unknown request id                                  */
+} ga_status;
+
+typedef enum {
+  GA_FIT_SQ = 0,
+  GA_FIT_ABS = 1,
+  GA_FIT_NNZ = 2,
+  GA_FIT_SQ_PLUS_NNZ = 3,
+  GA_FIT_F1 = 4,
+  GA_FIT_F2 = 5
+} ga_fitness_kind;
+
+typedef enum {
+  /* Tournament selection over the previous generation, optional elitism.  */
+  GA_SEL_TOURNAMENT = 0,
+  /* The paper's truncation (Sec. 3.3): n = 4N; the best 2N of the 4N
+   * matrices become the parents in random order; pairs (P_k, P_{k+N}) make
+   * offspring O_k, O_{N+k} in slots 2N + k and 3N + k.                      */
+  GA_SEL_PAPER = 1
+} ga_selection_kind;
+
+enum {
+  GA_STOP_ON_FOUND = 1u  /* ga_run: stop at the first generation with key 0 */
+};
+
+typedef struct {
+  uint32_t m;               /* order: m % 4 == 0, 4 <= m <= 64               */
+  uint32_t n;               /* population size (>= 2; paper mode: n = 4N)    */
+  uint64_t seed;            /* Philox key                                    */
+  uint32_t fitness;         /* ga_fitness_kind                               */
+  uint32_t selection;       /* ga_selection_kind                             */
+  uint32_t tournament_k;    /* contestants per tournament, 1..64             */
+  uint32_t elite;           /* tournament mode: elites kept, < n, <= 65536;
+                               paper mode: must be 0                         */
+  uint64_t xo_threshold;    /* crossover coin threshold, <= 2^32             */
+  uint64_t mut_threshold;   /* per-child mutation coin threshold, <= 2^32    */
+  uint32_t nc;              /* mutated columns per mutated child, <= 64      */
+  uint32_t nr;              /* row pairs per mutated child, <= 64            */
+  uint32_t max_generations; /* generation budget of ga_run                   */
+  uint32_t flags;           /* GA_STOP_ON_FOUND                              */
+} ga_config;
+
+typedef struct {
+  int32_t found;        /* 1 iff best_key == 0                               */
+  uint32_t generation;  /* generation of the reported population             */
+  uint32_t index;       /* slot of its best individual (lowest on ties)      */
+  uint32_t best_key;    /* that individual's key                             */
+  int8_t matrix[64 * 64]; /* that individual, int8 +1/-1, row-major m x m   */
+} ga_result;
+
+/* Message describing the calling thread's last error ("" if none). */
+const char* ga_last_error(void);
+
+/* GA_OK iff the configuration is valid (limits as documented above). */
+ga_status ga_validate(const ga_config* cfg);
+
+/* Number of uint32 words of one packed population: n * m * ceil(m / 32). */
+size_t ga_population_words(const ga_config* cfg);
+
+/*
+ * Initial population (Sec. 3.1).  Async.  pop: [n][m][W] words, written.
+ * Column 0 is all +1; column j >= 1 starts with rows 0..m/2-1 equal to -1
+ * and the rest +1, then is shuffled by Fisher-Yates: for i1 = 0..m-2,
+ * i2 = i1 + bounded(draw(stream 1, generation 0, index k, d = j*m + i1),
+ * m - i1), swap rows i1 and i2.
+ */
+ga_status ga_init_population(const ga_config* cfg, uint32_t* pop,
+                             void* stream);
+
+/*
+ * Fitness of every individual (Sec. 3.2, Sec. 4.2).  Async.
+ * pop: [n][m][W] words, read.  keys: [n] written with cfg->fitness's key.
+ * comps: nullable; [n][3] written with (SQ, ABS, NNZ).
+ */
+ga_status ga_fitness(const ga_config* cfg, const uint32_t* pop,
+                     uint32_t* keys, uint32_t* comps, void* stream);
+
+/*
+ * One generation, gen_in -> gen_in + 1 (Sec. 3, the loop body).  Async.
+ * pop_in/keys_in (read) hold generation gen_in with its keys; pop_out and
+ * keys_out (written, must not overlap the inputs) receive generation
+ * gen_in + 1 and its keys.  With G = gen_in + 1:
+ *
+ * Tournament mode.  e = cfg->elite.  Slots 0..e-1 receive the e individuals
+ * with the smallest (key, index), in increasing index order, unchanged.
+ * Child pair p = 0..ceil((n-e)/2)-1 has parents a, b: parent s in {0, 1} is
+ * the contestant with the smallest (key, index) among x_c = bounded(
+ * draw(2, G, p, s*t + c), n), c < t.  With u = draw(3, G, p, .): if
+ * u_0 < xo_threshold, cut = 1 + bounded(u_1, m - 1), child 0 takes columns
+ * < cut from a and the rest from b, child 1 the complement (Sec. 3.4);
+ * otherwise the children copy a and b.  Child c of the pair goes to slot
+ * e + 2p + c (dropped if >= n).  It is mutated iff u_{2+c} < mut_threshold:
+ * with q = 2p + c, columns col_jc = 1 + bounded(draw(4, G, q, jc), m - 1),
+ * jc < nc, row pairs r1 = bounded(draw(4, G, q, nc + 2 ir), m),
+ * r2 = bounded(draw(4, G, q, nc + 2 ir + 1), m), ir < nr; for each jc in
+ * order, for each ir in order, the entries (r1, col) and (r2, col) are
+ * negated iff they differ (Sec. 3.5, third method).
+ *
+ * Paper mode (Sec. 3.3-3.5).  N = n / 4.  The 2N individuals with the
+ * smallest (key, index), listed in index order as sel[0..2N-1], move to
+ * parent slots s = 0..2N-1 as sel[pi(s)] (keys carried along), where pi is a
+ * keyed permutation of [0, 2N): an eight-round Feistel network on 2h bits
+ * (4^h >= 2N), round r mapping (L, R) to (R, L xor (draw(5, G, R, r) mod
+ * 2^h)), cycle-walked into [0, 2N).  Pair k < N makes its children from
+ * parent slots k and k + N exactly as above and writes them to slots
+ * 2N + k and 3N + k.
+ *
+ * Selection ranks keys below 2^24 (all fitness kinds for m <= 64 are).
+ */
+ga_status ga_step(const ga_config* cfg, const uint32_t* pop_in,
+                  const uint32_t* keys_in, uint32_t* pop_out,
+                  uint32_t* keys_out, uint32_t gen_in, void* stream);
+
+/*
+ * A whole run (Sec. 3, the algorithm; Sec. 6 loop): init, fitness, then
+ * ga_step until a generation holds a key of 0 (with GA_STOP_ON_FOUND) or
+ * max_generations steps were made.  Synchronous: returns when done.
+ * pop_a, pop_b: two population buffers; generation g is left in pop_a if g
+ * is even, pop_b if odd.  keys_a, keys_b likewise.  out (host pointer) gets
+ * the final generation, its best (key, index) and that matrix.
+ */
+ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
+                 uint32_t* keys_a, uint32_t* keys_b, ga_result* out,
+                 void* stream);
+
+/*
+ * Several independent runs advanced together, one generation of every
+ * active population per launch (tournament mode only).  Synchronous.
+ * cfgs, outs: host arrays of count entries.  The library allocates the
+ * populations.  Every run's result equals what ga_run gives for it alone.
+ */
+ga_status ga_run_batch(const ga_config* cfgs, uint32_t count, ga_result* outs,
+                       void* stream);
+
+/* Count (on the host, synchronously) the matrices of pop breaking the
+ * invariants: column 0 words not 0, a column not balanced, bits set above
+ * row m - 1. */
+ga_status ga_check_invariants(const ga_config* cfg, const uint32_t* pop,
+                              uint32_t* bad_count, void* stream);
+
+/*
+ * Kernel timing, for measurement.  While enabled, ga_step and ga_run
+ * bracket each generation's children launch (the fused selection,
+ * crossover, mutation and fitness kernel) with HIP events recorded on the
+ * launch stream.  ga_timing_read waits for the recorded events and returns
+ * the mean duration in milliseconds and the number of timed launches since
+ * the last ga_timing_enable(1).  Not thread-safe; meant for benchmarks.
+ */
+ga_status ga_timing_enable(int on);
+ga_status ga_timing_read(double* mean_ms, uint64_t* launches);
+
+/* -------------------------------------------------------------------------
+ * Search server: continuous batching of independent runs (tournament mode).
+ * Requests are admitted while their device memory fits the HBM budget;
+ * admitted populations stay resident on the device and advance one
+ * generation per server tick together with every other active request; a
+ * request retires when a key reaches 0 (with GA_STOP_ON_FOUND) or its
+ * budget is spent.  Each result equals ga_run's for the same config.
+ * ---------------------------------------------------------------------- */
+typedef struct ga_server ga_server;
+
+/* Starts the server's worker thread on `device`.  *out: new handle. */
+ga_status ga_server_create(uint64_t hbm_budget_bytes, int device,
+                           ga_server** out);
+/* Non-blocking.  GA_EBUDGET if the request alone exceeds the budget. */
+ga_status ga_submit(ga_server* srv, const ga_config* cfg, uint64_t* request_id);
+/* GA_PENDING while running, GA_OK once *out holds the result. */
+ga_status ga_poll(ga_server* srv, uint64_t request_id, ga_result* out);
+/* Blocks until the request finishes; then as ga_poll. */
+ga_status ga_wait(ga_server* srv, uint64_t request_id, ga_result* out);
+/* Seconds from submission to retirement of a finished request. */
+ga_status ga_request_latency(ga_server* srv, uint64_t request_id,
+                             double* seconds);
+/* Stops the worker (pending requests are abandoned) and frees memory. */
+ga_status ga_server_destroy(ga_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GA_H */

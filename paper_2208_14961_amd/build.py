@@ -1,0 +1,96 @@
+"""Builds libga.so (HIP, gfx950) in-tree.
+
+Every .hip file under csrc/ is compiled to an object in parallel, then the
+objects are linked into paper_2208_14961_amd/libga.so.  Run as a script or
+call build().
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+ROOT = os.path.dirname(HERE)
+OBJ = os.path.join(ROOT, "_build")
+LIB = os.path.join(HERE, "libga.so")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+FLAGS = [
+    "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+    "-Wall", "-Wno-unused-function",
+    # no packed fp32 instructions anywhere in device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", os.path.join(ROOT, "include"),
+]
+
+
+def sources() -> list[str]:
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+
+
+def _device_asm(src: str) -> str:
+    """Device assembly of one source (gfx950), for the no-calls check."""
+    out = os.path.join(OBJ, os.path.basename(src)[:-4] + ".gfx950.s")
+    r = subprocess.run([HIPCC, *FLAGS, "--cuda-device-only", "-S", src, "-o", out],
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc -S failed on {src}:\n{r.stdout}")
+    return out
+
+
+def check_no_calls(asm_path: str) -> None:
+    """Every kernel must be call-free.  A body the compiler outlines into a
+    function longer than a conditional branch can reach gets long branches
+    that reuse the return-address registers, and such a function never
+    returns; keeping kernels free of calls rules that out."""
+    with open(asm_path) as f:
+        text = f.read()
+    if "s_swappc_b64" in text:
+        raise RuntimeError(f"{asm_path}: a kernel makes a function call (s_swappc_b64); "
+                           "force-inline the callee or split the kernel")
+
+
+def _compile(src: str) -> tuple[str, float]:
+    obj = os.path.join(OBJ, os.path.basename(src)[:-4] + ".o")
+    t0 = time.time()
+    r = subprocess.run([HIPCC, *FLAGS, "-c", src, "-o", obj],
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}")
+    return obj, time.time() - t0
+
+
+def build(verbose: bool = True) -> str:
+    """Compiles every source (always) and links libga.so; returns its path."""
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = sources()
+    kernel_srcs = [s for s in srcs if "__global__" in open(s).read()]
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        fut_obj = [ex.submit(_compile, s) for s in srcs]
+        fut_asm = [ex.submit(_device_asm, s) for s in kernel_srcs]
+        results = [f.result() for f in fut_obj]
+        for f in fut_asm:
+            check_no_calls(f.result())
+    if verbose:
+        for obj, dt in results:
+            print(f"  compiled {os.path.basename(obj)} in {dt:.1f}s", flush=True)
+    tmp = LIB + f".tmp{os.getpid()}"
+    r = subprocess.run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}",
+                        *[o for o, _ in results], "-o", tmp],
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    t = time.time()
+    path = build()
+    print(f"built {path} in {time.time() - t:.1f}s")
+    sys.exit(0)

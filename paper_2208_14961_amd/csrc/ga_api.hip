@@ -1,0 +1,459 @@
+// ga_api.hip -- the C ABI of libga (see include/ga.h): argument checks,
+// per-stream device workspaces, and the orchestration of the kernels for
+// single steps, whole runs and batches of runs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "ga_internal.h"
+
+namespace ga {
+
+static thread_local std::string g_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+}
+
+ga_status hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return GA_OK;
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? GA_ENOMEM : GA_EDEVICE;
+}
+
+#define GA_TRY(expr, what)                          \
+  do {                                              \
+    ga_status _s = hip_status((expr), (what));      \
+    if (_s != GA_OK) return _s;                     \
+  } while (0)
+
+uint32_t words_per_col(uint32_t m) { return (m + 31) / 32; }
+
+ga_status validate(const ga_config* c) {
+  if (!c) {
+    set_error("config is NULL");
+    return GA_EINVAL;
+  }
+  if (c->m < 4 || c->m > 64 || c->m % 4) {
+    set_error("m=%u: need m %% 4 == 0 and 4 <= m <= 64", c->m);
+    return GA_EINVAL;
+  }
+  if (c->n < 2 || c->n > kMaxN) {
+    set_error("n=%u: need 2 <= n <= %u", c->n, kMaxN);
+    return GA_EINVAL;
+  }
+  if (c->fitness > GA_FIT_F2 || c->selection > GA_SEL_PAPER) {
+    set_error("unknown fitness (%u) or selection (%u)", c->fitness,
+              c->selection);
+    return GA_EINVAL;
+  }
+  if (c->xo_threshold > (1ull << 32) || c->mut_threshold > (1ull << 32)) {
+    set_error("coin thresholds must be <= 2^32");
+    return GA_EINVAL;
+  }
+  if (c->nc > 64 || c->nr > 64 ||
+      (c->mut_threshold > 0 && (c->nc == 0 || c->nr == 0))) {
+    set_error("nc=%u nr=%u: need 1..64 when mutation is on", c->nc, c->nr);
+    return GA_EINVAL;
+  }
+  if (c->flags & ~(uint32_t)GA_STOP_ON_FOUND) {
+    set_error("unknown flags 0x%x", c->flags);
+    return GA_EINVAL;
+  }
+  if (c->selection == GA_SEL_TOURNAMENT) {
+    if (c->tournament_k < 1 || c->tournament_k > 64) {
+      set_error("tournament_k=%u: need 1..64", c->tournament_k);
+      return GA_EINVAL;
+    }
+    if (c->elite >= c->n || c->elite > kMaxElite) {
+      set_error("elite=%u: need elite < n and elite <= %u", c->elite,
+                kMaxElite);
+      return GA_EINVAL;
+    }
+  } else if (c->n % 4 || c->elite) {
+    set_error("paper mode: need n %% 4 == 0 and elite == 0");
+    return GA_EINVAL;
+  }
+  return GA_OK;
+}
+
+// Device workspace per (device, stream): the run state and the selection
+// scratch.  Work enqueued on one stream is ordered, so it never races with
+// itself; different streams get different workspaces.
+struct Workspace {
+  RunState* state = nullptr;
+  SelWork* sel = nullptr;
+  uint32_t* counter = nullptr;
+  RunState* host_state = nullptr;  // pinned mirrors for polling (two slots)
+  hipStream_t capture = nullptr;   // stream the generation graphs run on
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  // cached graph of one chunk of generations, valid for `graph_key`
+  hipGraphExec_t graph = nullptr;
+  std::vector<char> graph_key;
+};
+
+static std::mutex g_ws_mu;
+static std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
+
+static ga_status workspace(hipStream_t s, Workspace** out) {
+  int dev = 0;
+  GA_TRY(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  auto key = std::make_pair(dev, s);
+  auto it = g_ws.find(key);
+  if (it != g_ws.end()) {
+    *out = it->second;
+    return GA_OK;
+  }
+  Workspace* w = new Workspace();
+  GA_TRY(hipMalloc(&w->state, sizeof(RunState)), "hipMalloc(state)");
+  GA_TRY(hipMalloc(&w->sel, sizeof(SelWork)), "hipMalloc(selection)");
+  GA_TRY(hipMalloc(&w->counter, sizeof(uint32_t)), "hipMalloc(counter)");
+  GA_TRY(hipHostMalloc(&w->host_state, 2 * sizeof(RunState),
+                       hipHostMallocDefault),
+         "hipHostMalloc(state)");
+  GA_TRY(hipStreamCreateWithFlags(&w->capture, hipStreamNonBlocking),
+         "hipStreamCreate");
+  for (auto& e : w->ev)
+    GA_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming),
+           "hipEventCreate");
+  // the histograms and counters start at zero; the kernels restore zeros
+  GA_TRY(hipMemset(w->sel, 0, sizeof(SelWork)), "hipMemset(selection)");
+  g_ws[key] = w;
+  *out = w;
+  return GA_OK;
+}
+
+PopDesc make_desc(const ga_config* c, uint32_t* pa, uint32_t* pb,
+                         uint32_t* ka, uint32_t* kb, RunState* st,
+                         uint32_t max_gen, uint32_t stop_on_found) {
+  PopDesc d;
+  memset(&d, 0, sizeof d);
+  d.pop_a = pa;
+  d.pop_b = pb;
+  d.keys_a = ka;
+  d.keys_b = kb;
+  d.state = st;
+  d.seed = c->seed;
+  d.xo_thr = c->xo_threshold;
+  d.mut_thr = c->mut_threshold;
+  d.m = c->m;
+  d.n = c->n;
+  d.t = c->tournament_k;
+  d.nc = c->nc;
+  d.nr = c->nr;
+  d.kind = c->fitness;
+  d.paper = c->selection == GA_SEL_PAPER;
+  if (d.paper) {
+    d.elite = c->n / 2;   // offspring occupy slots 2N .. 4N-1
+    d.nchild = c->n / 2;
+  } else {
+    d.elite = c->elite;
+    d.nchild = c->n - c->elite;
+  }
+  d.max_gen = max_gen;
+  d.stop_on_found = stop_on_found;
+  d.block_begin = 0;
+  d.nblocks = (d.nchild + kBlock - 1) / kBlock;
+  return d;
+}
+
+// Optional event timing of the children launches (ga_timing_*).
+struct Timing {
+  bool on = false;
+  std::vector<hipEvent_t> pool;     // reusable events
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
+  size_t used = 0;
+};
+static Timing g_timing;
+
+static hipEvent_t timing_event() {
+  if (g_timing.used == g_timing.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_timing.pool.push_back(e);
+  }
+  return g_timing.pool[g_timing.used++];
+}
+
+static uint32_t select_count(const ga_config* c) {
+  if (c->selection == GA_SEL_PAPER) return c->n / 2;
+  return c->elite;
+}
+
+// Enqueues one generation of a single population (the state says which).
+static ga_status enqueue_generation(const ga_config* c, const PopDesc& d,
+                                    Workspace* w, hipStream_t s) {
+  const uint32_t cnt = select_count(c);
+  if (cnt > 0)
+    GA_TRY(launch_select(c, d.pop_a, d.pop_b, d.keys_a, d.keys_b, cnt, w->sel,
+                         d.state, s),
+           "selection kernels");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (g_timing.on) {
+    e0 = timing_event();
+    e1 = timing_event();
+    if (e0 && e1) GA_TRY(hipEventRecord(e0, s), "hipEventRecord");
+  }
+  GA_TRY(launch_children_one(d, s), "children kernel");
+  if (e0 && e1) {
+    GA_TRY(hipEventRecord(e1, s), "hipEventRecord");
+    g_timing.marks.emplace_back(e0, e1);
+  }
+  return GA_OK;
+}
+
+static void unpack_matrix(uint32_t m, const uint32_t* words, int8_t* out) {
+  const uint32_t W = words_per_col(m);
+  memset(out, 0, 64 * 64);
+  for (uint32_t r = 0; r < m; ++r)
+    for (uint32_t j = 0; j < m; ++j) {
+      const uint32_t bit = (words[j * W + r / 32] >> (r % 32)) & 1u;
+      out[r * m + j] = bit ? -1 : 1;
+    }
+}
+
+// Fills `out` from a finished run's state and its final buffers.
+ga_status read_result(const ga_config* c, const RunState& hs,
+                             const uint32_t* pop_a, const uint32_t* pop_b,
+                             ga_result* out) {
+  const uint32_t g = hs.final_gen;
+  const unsigned long long b = hs.best[g & 1u];
+  out->generation = g;
+  out->best_key = (uint32_t)(b >> 32);
+  out->index = (uint32_t)(b & 0xffffffffu);
+  out->found = out->best_key == 0;
+  const uint32_t mw = c->m * words_per_col(c->m);
+  std::vector<uint32_t> words(mw);
+  const uint32_t* src = ((g & 1u) ? pop_b : pop_a) + (size_t)out->index * mw;
+  GA_TRY(hipMemcpy(words.data(), src, mw * sizeof(uint32_t),
+                   hipMemcpyDeviceToHost),
+         "hipMemcpy(best matrix)");
+  unpack_matrix(c->m, words.data(), out->matrix);
+  return GA_OK;
+}
+
+}  // namespace ga
+
+using namespace ga;
+
+extern "C" {
+
+const char* ga_last_error(void) { return g_error.c_str(); }
+
+ga_status ga_validate(const ga_config* cfg) { return validate(cfg); }
+
+size_t ga_population_words(const ga_config* cfg) {
+  if (validate(cfg) != GA_OK) return 0;
+  return (size_t)cfg->n * cfg->m * words_per_col(cfg->m);
+}
+
+ga_status ga_init_population(const ga_config* cfg, uint32_t* pop,
+                             void* stream) {
+  ga_status st = validate(cfg);
+  if (st != GA_OK) return st;
+  if (!pop) {
+    set_error("pop is NULL");
+    return GA_EINVAL;
+  }
+  GA_TRY(launch_init(cfg, pop, (hipStream_t)stream), "init kernel");
+  return GA_OK;
+}
+
+ga_status ga_fitness(const ga_config* cfg, const uint32_t* pop,
+                     uint32_t* keys, uint32_t* comps, void* stream) {
+  ga_status st = validate(cfg);
+  if (st != GA_OK) return st;
+  if (!pop || !keys) {
+    set_error("pop or keys is NULL");
+    return GA_EINVAL;
+  }
+  GA_TRY(launch_fitness(cfg, pop, keys, comps, nullptr, (hipStream_t)stream),
+         "fitness kernel");
+  return GA_OK;
+}
+
+ga_status ga_step(const ga_config* cfg, const uint32_t* pop_in,
+                  const uint32_t* keys_in, uint32_t* pop_out,
+                  uint32_t* keys_out, uint32_t gen_in, void* stream) {
+  ga_status st = validate(cfg);
+  if (st != GA_OK) return st;
+  if (!pop_in || !keys_in || !pop_out || !keys_out || pop_in == pop_out ||
+      keys_in == keys_out) {
+    set_error("ga_step needs four distinct non-NULL buffers");
+    return GA_EINVAL;
+  }
+  if (gen_in == 0xffffffffu) {
+    set_error("gen_in too large");
+    return GA_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  Workspace* w;
+  st = workspace(s, &w);
+  if (st != GA_OK) return st;
+  // generation g lives in the "a" buffers iff g is even
+  uint32_t* pi = const_cast<uint32_t*>(pop_in);
+  uint32_t* ki = const_cast<uint32_t*>(keys_in);
+  const bool odd = gen_in & 1u;
+  PopDesc d = make_desc(cfg, odd ? pop_out : pi, odd ? pi : pop_out,
+                        odd ? keys_out : ki, odd ? ki : keys_out, w->state,
+                        0xffffffffu, 0);
+  GA_TRY(launch_set_state(w->state, gen_in, s), "state kernel");
+  return enqueue_generation(cfg, d, w, s);
+}
+
+ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
+                 uint32_t* keys_a, uint32_t* keys_b, ga_result* out,
+                 void* stream) {
+  ga_status st = validate(cfg);
+  if (st != GA_OK) return st;
+  if (!pop_a || !pop_b || !keys_a || !keys_b || !out || pop_a == pop_b ||
+      keys_a == keys_b) {
+    set_error("ga_run needs distinct non-NULL buffers and a result");
+    return GA_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  Workspace* w;
+  st = workspace(s, &w);
+  if (st != GA_OK) return st;
+  const uint32_t stop_on_found = (cfg->flags & GA_STOP_ON_FOUND) ? 1u : 0u;
+  PopDesc d = make_desc(cfg, pop_a, pop_b, keys_a, keys_b, w->state,
+                        cfg->max_generations, stop_on_found);
+  GA_TRY(launch_reset_state(w->state, s), "state kernel");
+  GA_TRY(launch_init(cfg, pop_a, s), "init kernel");
+  GA_TRY(launch_fitness(cfg, pop_a, keys_a, nullptr, w->state, s),
+         "fitness kernel");
+  GA_TRY(launch_gen0_finish(w->state, stop_on_found, cfg->max_generations, s),
+         "state kernel");
+  // Generations run in chunks: one captured graph of `chunk` generations,
+  // replayed; its kernels read the generation number from the run state and
+  // return at once after the run has stopped.  The host reads the state of
+  // chunk k while chunk k+1 runs.
+  const uint32_t chunk = std::min<uint32_t>(64, std::max<uint32_t>(1, cfg->max_generations));
+  const uint32_t nchunks = (cfg->max_generations + chunk - 1) / chunk;
+  if (g_timing.on) {
+    // measurement mode: direct launches, each children kernel timed
+    for (uint32_t i = 0; i < cfg->max_generations; ++i) {
+      st = enqueue_generation(cfg, d, w, s);
+      if (st != GA_OK) return st;
+    }
+  } else if (nchunks > 0) {
+    std::vector<char> key(sizeof(PopDesc) + sizeof(ga_config));
+    memcpy(key.data(), &d, sizeof(PopDesc));
+    memcpy(key.data() + sizeof(PopDesc), cfg, sizeof(ga_config));
+    if (!w->graph || w->graph_key != key) {
+      if (w->graph) {
+        GA_TRY(hipGraphExecDestroy(w->graph), "hipGraphExecDestroy");
+        w->graph = nullptr;
+      }
+      hipGraph_t g;
+      GA_TRY(hipStreamBeginCapture(w->capture, hipStreamCaptureModeThreadLocal),
+             "hipStreamBeginCapture");
+      for (uint32_t i = 0; i < chunk && st == GA_OK; ++i)
+        st = enqueue_generation(cfg, d, w, w->capture);
+      hipError_t ce = hipStreamEndCapture(w->capture, &g);
+      if (st != GA_OK) return st;
+      GA_TRY(ce, "hipStreamEndCapture");
+      GA_TRY(hipGraphInstantiate(&w->graph, g, nullptr, nullptr, 0),
+             "hipGraphInstantiate");
+      GA_TRY(hipGraphDestroy(g), "hipGraphDestroy");
+      w->graph_key = key;
+    }
+    // the capture stream starts after the work already enqueued on s
+    GA_TRY(hipEventRecord(w->ev[2], s), "hipEventRecord");
+    GA_TRY(hipStreamWaitEvent(w->capture, w->ev[2], 0), "hipStreamWaitEvent");
+    auto launch_chunk = [&](uint32_t k) -> ga_status {
+      GA_TRY(hipGraphLaunch(w->graph, w->capture), "hipGraphLaunch");
+      GA_TRY(hipMemcpyAsync(&w->host_state[k & 1], w->state, sizeof(RunState),
+                            hipMemcpyDeviceToHost, w->capture),
+             "hipMemcpyAsync(state)");
+      GA_TRY(hipEventRecord(w->ev[k & 1], w->capture), "hipEventRecord");
+      return GA_OK;
+    };
+    st = launch_chunk(0);
+    if (st != GA_OK) return st;
+    for (uint32_t k = 0; k < nchunks; ++k) {
+      if (k + 1 < nchunks) {
+        st = launch_chunk(k + 1);
+        if (st != GA_OK) return st;
+      }
+      GA_TRY(hipEventSynchronize(w->ev[k & 1]), "hipEventSynchronize");
+      if (w->host_state[k & 1].stop) break;
+    }
+    // s continues after everything the capture stream did
+    GA_TRY(hipEventRecord(w->ev[2], w->capture), "hipEventRecord");
+    GA_TRY(hipStreamWaitEvent(s, w->ev[2], 0), "hipStreamWaitEvent");
+  }
+  GA_TRY(hipMemcpyAsync(w->host_state, w->state, sizeof(RunState),
+                        hipMemcpyDeviceToHost, s),
+         "hipMemcpyAsync(state)");
+  GA_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  RunState hs = *w->host_state;
+  if (!hs.stop) {
+    set_error("run did not reach its stop condition");
+    return GA_EDEVICE;
+  }
+  return read_result(cfg, hs, pop_a, pop_b, out);
+}
+
+ga_status ga_timing_enable(int on) {
+  g_timing.on = on != 0;
+  if (g_timing.on) {
+    g_timing.marks.clear();
+    g_timing.used = 0;
+  }
+  return GA_OK;
+}
+
+ga_status ga_timing_read(double* mean_ms, uint64_t* launches) {
+  if (!mean_ms || !launches) {
+    set_error("ga_timing_read needs two outputs");
+    return GA_EINVAL;
+  }
+  double total = 0;
+  for (auto& m : g_timing.marks) {
+    GA_TRY(hipEventSynchronize(m.second), "hipEventSynchronize");
+    float ms = 0;
+    GA_TRY(hipEventElapsedTime(&ms, m.first, m.second), "hipEventElapsedTime");
+    total += ms;
+  }
+  *launches = g_timing.marks.size();
+  *mean_ms = g_timing.marks.empty() ? 0.0 : total / g_timing.marks.size();
+  return GA_OK;
+}
+
+ga_status ga_check_invariants(const ga_config* cfg, const uint32_t* pop,
+                              uint32_t* bad_count, void* stream) {
+  ga_status st = validate(cfg);
+  if (st != GA_OK) return st;
+  if (!pop || !bad_count) {
+    set_error("pop or bad_count is NULL");
+    return GA_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  Workspace* w;
+  st = workspace(s, &w);
+  if (st != GA_OK) return st;
+  GA_TRY(hipMemsetAsync(w->counter, 0, sizeof(uint32_t), s), "hipMemsetAsync");
+  GA_TRY(launch_check(cfg, pop, w->counter, s), "check kernel");
+  GA_TRY(hipMemcpyAsync(bad_count, w->counter, sizeof(uint32_t),
+                        hipMemcpyDeviceToHost, s),
+         "hipMemcpyAsync");
+  GA_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return GA_OK;
+}
+
+}  // extern "C"

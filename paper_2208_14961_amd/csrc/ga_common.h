@@ -1,0 +1,76 @@
+// ga_common.h -- block-level helpers shared by libga's kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ga_internal.h"
+
+namespace ga {
+
+__device__ __forceinline__ uint32_t ld_acq(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block-wide minimum of a 64-bit value; the result is valid in thread 0.
+__device__ __forceinline__ unsigned long long block_min_u64(
+    unsigned long long v) {
+  __shared__ unsigned long long s_min[kBlock / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off, 64);
+    v = o < v ? o : v;
+  }
+  const int wave = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) s_min[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w)
+      v = s_min[w] < v ? s_min[w] : v;
+  }
+  return v;
+}
+
+// Exclusive prefix sum over the block (blockDim.x == kBlock); also returns
+// the block total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v,
+                                                         uint32_t* total) {
+  __shared__ uint32_t s_wave[kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x / 64;
+  uint32_t incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) s_wave[wave] = incl;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    const uint32_t x = s_wave[w];
+    if (w < wave) base += x;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + incl - v;
+}
+
+__device__ __forceinline__ bool last_block(uint32_t* counter) {
+  __shared__ bool s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    if (s_last) __threadfence();
+  }
+  __syncthreads();
+  return s_last;
+}
+
+static inline uint32_t cdiv(uint64_t a, uint64_t b) {
+  return (uint32_t)((a + b - 1) / b);
+}
+
+}  // namespace ga

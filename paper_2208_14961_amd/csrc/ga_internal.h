@@ -1,0 +1,144 @@
+// ga_internal.h -- structures and launchers shared by libga's own sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ga.h"
+
+namespace ga {
+
+constexpr uint32_t kMaxN = 1u << 24;        // population size limit
+constexpr uint32_t kMaxElite = 1u << 16;    // elite count limit
+constexpr uint32_t kKeyBits = 24;           // selection ranks keys < 2^24
+constexpr int kBlock = 256;                 // threads per block, step kernels
+constexpr int kSelTile = 2048;              // elements per block, selection
+constexpr int kMaxSelBlocks = 8192;         // kMaxN / kSelTile
+
+// Device-resident progress of one run.  Generation g of the run lives in
+// buffer A if g is even, B if odd.
+struct RunState {
+  unsigned long long best[2];  // min (key << 32 | slot) of gens of parity 0/1
+  uint32_t gen;                // last completed generation
+  uint32_t stop;               // 1 once the run is over
+  uint32_t final_gen;          // generation reported when stopped
+  uint32_t blocks_done;        // last-block detection of the step kernel
+  uint32_t pad[2];
+};
+
+// One population in a step launch.
+struct PopDesc {
+  uint32_t* pop_a;
+  uint32_t* pop_b;
+  uint32_t* keys_a;
+  uint32_t* keys_b;
+  RunState* state;
+  uint64_t seed;
+  uint64_t xo_thr;
+  uint64_t mut_thr;
+  uint32_t m, n;
+  uint32_t elite;        // first child slot (tournament); 2N (paper)
+  uint32_t nchild;       // children produced per generation
+  uint32_t t, nc, nr, kind;
+  uint32_t paper;        // 1: paper mode (parents in slots k, k+N of output)
+  uint32_t max_gen;
+  uint32_t stop_on_found;
+  uint32_t block_begin;  // first block of this population in the launch
+  uint32_t nblocks;      // blocks of this population
+  uint32_t pad;
+};
+
+// Workspace of the selection pipeline of one population.
+struct SelWork {
+  uint32_t h1[4096];
+  uint32_t h2[4096];
+  uint32_t blk_less[kMaxSelBlocks];
+  uint32_t blk_eq[kMaxSelBlocks];
+  uint32_t bucket, below, T, r;   // results of the radix select
+  uint32_t cnt[4];                // last-block counters
+};
+
+// ---- launchers (ga_kernels.hip) ----------------------------------------
+hipError_t launch_init(const ga_config* c, uint32_t* pop, hipStream_t s);
+// keys for all n; comps nullable; st nullable (then no best tracking)
+hipError_t launch_fitness(const ga_config* c, const uint32_t* pop,
+                          uint32_t* keys, uint32_t* comps, RunState* st,
+                          hipStream_t s);
+// selection of the `count` smallest (key, index) of generation g (read from
+// the state) into generation g + 1 (elitism: slot = rank in index order;
+// paper mode: slot = pi^-1(rank)); buffers by parity as in RunState
+hipError_t launch_select(const ga_config* c, uint32_t* pop_a, uint32_t* pop_b,
+                         uint32_t* keys_a, uint32_t* keys_b, uint32_t count,
+                         SelWork* ws, RunState* st, hipStream_t s);
+// children of every population in descs (device array); all of order m if
+// m <= 32, else all of orders 36..64
+hipError_t launch_children(const PopDesc* descs_dev, const uint32_t* block_pop,
+                           uint32_t total_blocks, uint32_t m, hipStream_t s);
+// children of one population (descriptor passed by value)
+hipError_t launch_children_one(const PopDesc& d, hipStream_t s);
+hipError_t launch_set_state(RunState* st, uint32_t gen, hipStream_t s);
+hipError_t launch_gen0_finish(RunState* st, uint32_t stop_on_found,
+                              uint32_t max_gen, hipStream_t s);
+hipError_t launch_reset_state(RunState* st, hipStream_t s);
+hipError_t launch_check(const ga_config* c, const uint32_t* pop,
+                        uint32_t* bad, hipStream_t s);
+
+// ---- helpers (ga_api.hip) -----------------------------------------------
+void set_error(const char* fmt, ...);
+ga_status hip_status(hipError_t e, const char* what);
+ga_status validate(const ga_config* c);
+uint32_t words_per_col(uint32_t m);
+PopDesc make_desc(const ga_config* c, uint32_t* pa, uint32_t* pb, uint32_t* ka,
+                  uint32_t* kb, RunState* st, uint32_t max_gen,
+                  uint32_t stop_on_found);
+// Copies the best individual of a finished run into out (synchronous).
+ga_status read_result(const ga_config* c, const RunState& hs,
+                      const uint32_t* pop_a, const uint32_t* pop_b,
+                      ga_result* out);
+
+// ---- several independent runs advanced together (ga_multi.hip) ----------
+// Device memory of one run: two populations, two key arrays.
+struct RunBuffers {
+  uint32_t* pop_a = nullptr;
+  uint32_t* pop_b = nullptr;
+  uint32_t* keys_a = nullptr;
+  uint32_t* keys_b = nullptr;
+  void* base = nullptr;   // single allocation holding all four
+};
+size_t run_bytes(const ga_config* c);
+ga_status alloc_run(const ga_config* c, RunBuffers* b);
+void free_run(RunBuffers* b);
+
+// Starts runs in place: state reset, initial population and its fitness.
+ga_status start_runs(const ga_config* cfgs, const RunBuffers* bufs,
+                     RunState* states, uint32_t count, hipStream_t s);
+
+// Launch tables of a set of runs: one descriptor per run, and the map from
+// a block of the children launch to its run, per group (one group per order
+// up to 32, one group for orders 36..64).
+class MultiLaunch {
+ public:
+  ~MultiLaunch();
+  // descs: one per run (state pointers set); rebuilds and uploads the tables
+  ga_status set(const PopDesc* descs, uint32_t count, hipStream_t s);
+  // one generation of every run that has not stopped
+  ga_status enqueue_generation(hipStream_t s);
+  // `gens` generations as one graph launch on s (captured on first use
+  // after set(); s must not be the null stream)
+  ga_status launch_chunk(uint32_t gens, hipStream_t s);
+
+ private:
+  struct Group {
+    uint32_t m = 0;                  // order (orders > 32 share group m = 64)
+    PopDesc* desc = nullptr;
+    uint32_t* map = nullptr;
+    size_t cap_desc = 0, cap_map = 0;
+    uint32_t nblocks = 0;
+  };
+  Group groups_[9];                  // orders 4..32 step 4, then 36..64
+  hipGraphExec_t graph_ = nullptr;
+  uint32_t graph_gens_ = 0;
+  hipStream_t capture_ = nullptr;
+};
+
+}  // namespace ga

@@ -1,0 +1,236 @@
+// ga_kernels.hip -- initialization, standalone fitness, run-state and
+// invariant-check kernels of libga (gfx950) and their launchers.
+//
+// One lane per individual.  A lane keeps the packed columns of its matrix
+// in registers (orders up to 32) or reads them in register tiles (orders
+// 36..64), so the Gram matrix is never materialized: each off-diagonal
+// entry is one xor and one popcount per word, reduced into the key on the
+// fly.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "ga_common.h"
+#include "ga_device.h"
+
+namespace ga {
+
+// ---------------------------------------------------------------------------
+// Initial population (Sec. 3.1): one thread per (matrix k, column j).
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kBlock) void init_kernel(uint32_t* pop,
+                                                      uint32_t n,
+                                                      uint64_t seed) {
+  constexpr int W = (M + 31) / 32;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (uint64_t)n * M) return;
+  const uint32_t k = (uint32_t)(t / M), j = (uint32_t)(t % M);
+  uint64_t v = 0;
+  if (j > 0) {
+    v = (M / 2 == 64) ? ~0ull : ((1ull << (M / 2)) - 1ull);  // rows < M/2 = -1
+    // Fisher-Yates over rows: draws d = j*M + i1 are whole blocks j*M/4 ...
+#pragma unroll
+    for (int b = 0; b < M / 4; ++b) {
+      const U4 u = draw_block(seed, kStreamInit, 0, k, j * (M / 4) + b);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int i1 = 4 * b + w;
+        if (i1 >= M - 1) break;
+        const uint32_t i2 = (uint32_t)i1 + bounded(u[w], (uint32_t)(M - i1));
+        const uint64_t b1 = (v >> i1) & 1ull, b2 = (v >> i2) & 1ull;
+        if (b1 != b2) v ^= (1ull << i1) | (1ull << i2);
+      }
+    }
+  }
+  uint32_t* dst = pop + ((size_t)k * M + j) * W;
+  dst[0] = (uint32_t)v;
+  if (W > 1) dst[W - 1] = (uint32_t)(v >> 32);
+}
+
+// ---------------------------------------------------------------------------
+// Standalone fitness (Sec. 3.2): one lane per individual.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void fitness_epilogue(uint32_t k, uint32_t key,
+                                                 const uint32_t* out3,
+                                                 uint32_t* keys, uint32_t* comps,
+                                                 unsigned long long* best) {
+  keys[k] = key;
+  if (comps) {
+    comps[3 * (size_t)k + 0] = out3[0];
+    comps[3 * (size_t)k + 1] = out3[1];
+    comps[3 * (size_t)k + 2] = out3[2];
+  }
+  *best = ((unsigned long long)key << 32) | k;
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void fitness_kernel(
+    const uint32_t* __restrict__ pop, uint32_t n, uint32_t kind,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ comps, RunState* st) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long best = ~0ull;
+  if (k < n) {
+    Cols<M> c;
+    load_cols<M>(pop + (size_t)k * M, c);
+    uint32_t out3[3];
+    const uint32_t key = fitness<M>(c, kind, comps != nullptr, out3);
+    fitness_epilogue(k, key, out3, keys, comps, &best);
+  }
+  if (st) {
+    best = block_min_u64(best);
+    if (threadIdx.x == 0) atomicMin(&st->best[0], best);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void fitness_kernel_w2(
+    const uint32_t* __restrict__ pop, uint32_t n, uint32_t m, uint32_t kind,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ comps, RunState* st) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long best = ~0ull;
+  if (k < n) {
+    uint32_t out3[3];
+    const uint32_t key =
+        fitness_w2(pop + (size_t)k * 2 * m, m, kind, comps != nullptr, out3);
+    fitness_epilogue(k, key, out3, keys, comps, &best);
+  }
+  if (st) {
+    best = block_min_u64(best);
+    if (threadIdx.x == 0) atomicMin(&st->best[0], best);
+  }
+}
+
+__global__ void reset_state_kernel(RunState* st) {
+  st->best[0] = ~0ull;
+  st->best[1] = ~0ull;
+  st->gen = 0;
+  st->stop = 0;
+  st->final_gen = 0;
+  st->blocks_done = 0;
+}
+
+__global__ void gen0_finish_kernel(RunState* st, uint32_t stop_on_found,
+                                   uint32_t max_gen) {
+  const uint32_t key = (uint32_t)(st->best[0] >> 32);
+  st->gen = 0;
+  st->best[1] = ~0ull;
+  if ((stop_on_found && key == 0) || max_gen == 0) {
+    st->final_gen = 0;
+    st->stop = 1;
+  }
+}
+
+__global__ void set_state_kernel(RunState* st, uint32_t gen) {
+  st->gen = gen;
+  st->stop = 0;
+  st->final_gen = 0;
+  st->blocks_done = 0;
+  st->best[(gen + 1) & 1u] = ~0ull;
+}
+
+// ---------------------------------------------------------------------------
+// Invariant check: column 0 zero, other columns balanced, no bits >= m.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void check_kernel(const uint32_t* pop,
+                                                       uint32_t n, uint32_t m,
+                                                       uint32_t* bad) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t W = (m + 31) / 32;
+  const uint32_t* Q = pop + (size_t)k * m * W;
+  bool ok = true;
+  for (uint32_t w = 0; w < W; ++w) ok &= Q[w] == 0;
+  for (uint32_t j = 1; j < m; ++j) {
+    uint32_t pc = 0;
+    for (uint32_t w = 0; w < W; ++w) {
+      const uint32_t x = Q[j * W + w];
+      const uint32_t rows = (m > 32 * w) ? min(32u, m - 32 * w) : 0u;
+      const uint32_t valid = rows == 32 ? 0xffffffffu : ((1u << rows) - 1u);
+      ok &= (x & ~valid) == 0;
+      pc += __popc(x);
+    }
+    ok &= pc == m / 2;
+  }
+  if (!ok) atomicAdd(bad, 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+#define GA_DISPATCH_M(m, EXPR)                  \
+  switch (m) {                                  \
+    case 4: { constexpr int MM = 4; EXPR; } break;   \
+    case 8: { constexpr int MM = 8; EXPR; } break;   \
+    case 12: { constexpr int MM = 12; EXPR; } break; \
+    case 16: { constexpr int MM = 16; EXPR; } break; \
+    case 20: { constexpr int MM = 20; EXPR; } break; \
+    case 24: { constexpr int MM = 24; EXPR; } break; \
+    case 28: { constexpr int MM = 28; EXPR; } break; \
+    case 32: { constexpr int MM = 32; EXPR; } break; \
+    case 36: { constexpr int MM = 36; EXPR; } break; \
+    case 40: { constexpr int MM = 40; EXPR; } break; \
+    case 44: { constexpr int MM = 44; EXPR; } break; \
+    case 48: { constexpr int MM = 48; EXPR; } break; \
+    case 52: { constexpr int MM = 52; EXPR; } break; \
+    case 56: { constexpr int MM = 56; EXPR; } break; \
+    case 60: { constexpr int MM = 60; EXPR; } break; \
+    case 64: { constexpr int MM = 64; EXPR; } break; \
+    default: return hipErrorInvalidValue;       \
+  }
+
+hipError_t launch_init(const ga_config* c, uint32_t* pop, hipStream_t s) {
+  const uint32_t grid = cdiv((uint64_t)c->n * c->m, kBlock);
+  GA_DISPATCH_M(c->m, hipLaunchKernelGGL(init_kernel<MM>, dim3(grid),
+                                         dim3(kBlock), 0, s, pop, c->n,
+                                         c->seed));
+  return hipGetLastError();
+}
+
+hipError_t launch_fitness(const ga_config* c, const uint32_t* pop,
+                          uint32_t* keys, uint32_t* comps, RunState* st,
+                          hipStream_t s) {
+  const uint32_t grid = cdiv(c->n, kBlock);
+  if (c->m > 32) {
+    hipLaunchKernelGGL(fitness_kernel_w2, dim3(grid), dim3(kBlock), 0, s, pop,
+                       c->n, c->m, c->fitness, keys, comps, st);
+    return hipGetLastError();
+  }
+  switch (c->m) {
+#define GA_FIT_CASE(MM)                                                       \
+  case MM:                                                                    \
+    hipLaunchKernelGGL(fitness_kernel<MM>, dim3(grid), dim3(kBlock), 0, s,    \
+                       pop, c->n, c->fitness, keys, comps, st);              \
+    break;
+    GA_FIT_CASE(4) GA_FIT_CASE(8) GA_FIT_CASE(12) GA_FIT_CASE(16)
+    GA_FIT_CASE(20) GA_FIT_CASE(24) GA_FIT_CASE(28) GA_FIT_CASE(32)
+#undef GA_FIT_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_state(RunState* st, hipStream_t s) {
+  hipLaunchKernelGGL(reset_state_kernel, dim3(1), dim3(1), 0, s, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_gen0_finish(RunState* st, uint32_t stop_on_found,
+                              uint32_t max_gen, hipStream_t s) {
+  hipLaunchKernelGGL(gen0_finish_kernel, dim3(1), dim3(1), 0, s, st,
+                     stop_on_found, max_gen);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(RunState* st, uint32_t gen, hipStream_t s) {
+  hipLaunchKernelGGL(set_state_kernel, dim3(1), dim3(1), 0, s, st, gen);
+  return hipGetLastError();
+}
+
+hipError_t launch_check(const ga_config* c, const uint32_t* pop, uint32_t* bad,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(check_kernel, dim3(cdiv(c->n, kBlock)), dim3(kBlock), 0,
+                     s, pop, c->n, c->m, bad);
+  return hipGetLastError();
+}
+
+}  // namespace ga

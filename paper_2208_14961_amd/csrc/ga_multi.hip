@@ -1,0 +1,253 @@
+// ga_multi.hip -- several independent runs advanced one generation per
+// launch: the batched entry point ga_run_batch and the building blocks the
+// search server shares with it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "ga_common.h"
+
+namespace ga {
+
+#define GA_TRY(expr, what)                          \
+  do {                                              \
+    ga_status _s = hip_status((expr), (what));      \
+    if (_s != GA_OK) return _s;                     \
+  } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t run_bytes(const ga_config* c) {
+  const size_t pop = (size_t)c->n * c->m * words_per_col(c->m) * 4;
+  const size_t keys = (size_t)c->n * 4;
+  return 2 * align256(pop) + 2 * align256(keys);
+}
+
+ga_status alloc_run(const ga_config* c, RunBuffers* b) {
+  const size_t pop = align256((size_t)c->n * c->m * words_per_col(c->m) * 4);
+  const size_t keys = align256((size_t)c->n * 4);
+  char* base = nullptr;
+  GA_TRY(hipMalloc(&base, 2 * pop + 2 * keys), "hipMalloc(run)");
+  b->base = base;
+  b->pop_a = reinterpret_cast<uint32_t*>(base);
+  b->pop_b = reinterpret_cast<uint32_t*>(base + pop);
+  b->keys_a = reinterpret_cast<uint32_t*>(base + 2 * pop);
+  b->keys_b = reinterpret_cast<uint32_t*>(base + 2 * pop + keys);
+  return GA_OK;
+}
+
+void free_run(RunBuffers* b) {
+  if (b->base) (void)hipFree(b->base);
+  *b = RunBuffers();
+}
+
+MultiLaunch::~MultiLaunch() {
+  if (graph_) (void)hipGraphExecDestroy(graph_);
+  if (capture_) (void)hipStreamDestroy(capture_);
+  for (Group& g : groups_) {
+    if (g.desc) (void)hipFree(g.desc);
+    if (g.map) (void)hipFree(g.map);
+  }
+}
+
+static int group_of(uint32_t m) { return m <= 32 ? (int)(m / 4) - 1 : 8; }
+
+ga_status MultiLaunch::set(const PopDesc* descs, uint32_t count,
+                           hipStream_t s) {
+  if (graph_) {
+    GA_TRY(hipGraphExecDestroy(graph_), "hipGraphExecDestroy");
+    graph_ = nullptr;
+  }
+  for (int gi = 0; gi < 9; ++gi) {
+    Group& g = groups_[gi];
+    g.m = gi < 8 ? 4u * (gi + 1) : 64u;
+    std::vector<PopDesc> ds;
+    std::vector<uint32_t> map;
+    for (uint32_t i = 0; i < count; ++i) {
+      if (group_of(descs[i].m) != gi) continue;
+      PopDesc d = descs[i];
+      d.block_begin = (uint32_t)map.size();
+      for (uint32_t b = 0; b < d.nblocks; ++b)
+        map.push_back((uint32_t)ds.size());
+      ds.push_back(d);
+    }
+    g.nblocks = (uint32_t)map.size();
+    if (ds.empty()) continue;
+    if (ds.size() > g.cap_desc) {
+      if (g.desc) GA_TRY(hipFree(g.desc), "hipFree");
+      g.cap_desc = ds.size() * 2;
+      GA_TRY(hipMalloc(&g.desc, g.cap_desc * sizeof(PopDesc)),
+             "hipMalloc(descs)");
+    }
+    if (map.size() > g.cap_map) {
+      if (g.map) GA_TRY(hipFree(g.map), "hipFree");
+      g.cap_map = map.size() * 2;
+      GA_TRY(hipMalloc(&g.map, g.cap_map * sizeof(uint32_t)),
+             "hipMalloc(block map)");
+    }
+    // synchronous copies: the tables change only between ticks
+    GA_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    GA_TRY(hipMemcpy(g.desc, ds.data(), ds.size() * sizeof(PopDesc),
+                     hipMemcpyHostToDevice),
+           "hipMemcpy(descs)");
+    GA_TRY(hipMemcpy(g.map, map.data(), map.size() * sizeof(uint32_t),
+                     hipMemcpyHostToDevice),
+           "hipMemcpy(block map)");
+  }
+  return GA_OK;
+}
+
+ga_status MultiLaunch::enqueue_generation(hipStream_t s) {
+  for (Group& g : groups_)
+    if (g.nblocks)
+      GA_TRY(launch_children(g.desc, g.map, g.nblocks, g.m, s),
+             "children kernel");
+  return GA_OK;
+}
+
+ga_status MultiLaunch::launch_chunk(uint32_t gens, hipStream_t s) {
+  if (!graph_ || graph_gens_ != gens) {
+    if (graph_) {
+      GA_TRY(hipGraphExecDestroy(graph_), "hipGraphExecDestroy");
+      graph_ = nullptr;
+    }
+    if (!capture_)
+      GA_TRY(hipStreamCreateWithFlags(&capture_, hipStreamNonBlocking),
+             "hipStreamCreate");
+    hipGraph_t g;
+    GA_TRY(hipStreamBeginCapture(capture_, hipStreamCaptureModeThreadLocal),
+           "hipStreamBeginCapture");
+    ga_status st = GA_OK;
+    for (uint32_t i = 0; i < gens && st == GA_OK; ++i)
+      st = enqueue_generation(capture_);
+    hipError_t ce = hipStreamEndCapture(capture_, &g);
+    if (st != GA_OK) return st;
+    GA_TRY(ce, "hipStreamEndCapture");
+    GA_TRY(hipGraphInstantiate(&graph_, g, nullptr, nullptr, 0),
+           "hipGraphInstantiate");
+    GA_TRY(hipGraphDestroy(g), "hipGraphDestroy");
+    graph_gens_ = gens;
+  }
+  GA_TRY(hipGraphLaunch(graph_, s), "hipGraphLaunch");
+  return GA_OK;
+}
+
+// Starts a run in place: state reset, initial population, its fitness.
+static ga_status start_run(const ga_config* c, const RunBuffers& b,
+                           RunState* st, hipStream_t s) {
+  const uint32_t stop_on_found = (c->flags & GA_STOP_ON_FOUND) ? 1u : 0u;
+  GA_TRY(launch_reset_state(st, s), "state kernel");
+  GA_TRY(launch_init(c, b.pop_a, s), "init kernel");
+  GA_TRY(launch_fitness(c, b.pop_a, b.keys_a, nullptr, st, s), "fitness kernel");
+  GA_TRY(launch_gen0_finish(st, stop_on_found, c->max_generations, s),
+         "state kernel");
+  return GA_OK;
+}
+
+ga_status start_runs(const ga_config* cfgs, const RunBuffers* bufs,
+                     RunState* states, uint32_t count, hipStream_t s) {
+  for (uint32_t i = 0; i < count; ++i) {
+    ga_status st = start_run(&cfgs[i], bufs[i], &states[i], s);
+    if (st != GA_OK) return st;
+  }
+  return GA_OK;
+}
+
+}  // namespace ga
+
+using namespace ga;
+
+extern "C" ga_status ga_run_batch(const ga_config* cfgs, uint32_t count,
+                                  ga_result* outs, void* stream) {
+  if (!cfgs || !outs || count == 0) {
+    set_error("ga_run_batch needs count > 0 configs and results");
+    return GA_EINVAL;
+  }
+  for (uint32_t i = 0; i < count; ++i) {
+    ga_status v = validate(&cfgs[i]);
+    if (v != GA_OK) return v;
+    if (cfgs[i].selection != GA_SEL_TOURNAMENT || cfgs[i].elite != 0) {
+      set_error("ga_run_batch: run %u: batched runs use tournament selection "
+                "without elites", i);
+      return GA_EINVAL;
+    }
+  }
+  // The batch runs on a private stream after the caller's stream is idle
+  // (the call is synchronous), so its generation chunks can be graphs.
+  GA_TRY(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+  hipStream_t s = nullptr;
+  GA_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+  std::vector<RunBuffers> bufs(count);
+  RunState* states = nullptr;
+  RunState* host = nullptr;
+  MultiLaunch ml;
+  ga_status rc = GA_OK;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(s);
+    for (auto& b : bufs) free_run(&b);
+    if (states) (void)hipFree(states);
+    if (host) (void)hipHostFree(host);
+    (void)hipStreamDestroy(s);
+  };
+  do {
+    for (uint32_t i = 0; i < count && rc == GA_OK; ++i)
+      rc = alloc_run(&cfgs[i], &bufs[i]);
+    if (rc != GA_OK) break;
+    rc = hip_status(hipMalloc(&states, count * sizeof(RunState)),
+                    "hipMalloc(states)");
+    if (rc != GA_OK) break;
+    rc = hip_status(hipHostMalloc(&host, count * sizeof(RunState),
+                                  hipHostMallocDefault),
+                    "hipHostMalloc(states)");
+    if (rc != GA_OK) break;
+    rc = start_runs(cfgs, bufs.data(), states, count, s);
+    if (rc != GA_OK) break;
+    std::vector<PopDesc> descs(count);
+    uint32_t gmax = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+      descs[i] = make_desc(&cfgs[i], bufs[i].pop_a, bufs[i].pop_b,
+                           bufs[i].keys_a, bufs[i].keys_b, &states[i],
+                           cfgs[i].max_generations,
+                           (cfgs[i].flags & GA_STOP_ON_FOUND) ? 1u : 0u);
+      gmax = std::max(gmax, cfgs[i].max_generations);
+    }
+    rc = ml.set(descs.data(), count, s);
+    if (rc != GA_OK) break;
+    const uint32_t chunk = std::min<uint32_t>(32, std::max<uint32_t>(gmax, 1));
+    uint32_t enq = 0;
+    bool all_stopped = false;
+    while (!all_stopped && enq < gmax) {
+      rc = ml.launch_chunk(chunk, s);
+      if (rc != GA_OK) break;
+      enq += chunk;
+      rc = hip_status(hipMemcpyAsync(host, states, count * sizeof(RunState),
+                                     hipMemcpyDeviceToHost, s),
+                      "hipMemcpyAsync(states)");
+      if (rc != GA_OK) break;
+      rc = hip_status(hipStreamSynchronize(s), "hipStreamSynchronize");
+      if (rc != GA_OK) break;
+      all_stopped = true;
+      for (uint32_t i = 0; i < count; ++i) all_stopped &= host[i].stop != 0;
+    }
+    if (rc != GA_OK) break;
+    rc = hip_status(hipMemcpyAsync(host, states, count * sizeof(RunState),
+                                   hipMemcpyDeviceToHost, s),
+                    "hipMemcpyAsync(states)");
+    if (rc != GA_OK) break;
+    rc = hip_status(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (rc != GA_OK) break;
+    for (uint32_t i = 0; i < count && rc == GA_OK; ++i) {
+      if (!host[i].stop) {
+        set_error("batched run %u did not reach its stop condition", i);
+        rc = GA_EDEVICE;
+        break;
+      }
+      rc = read_result(&cfgs[i], host[i], bufs[i].pop_a, bufs[i].pop_b,
+                       &outs[i]);
+    }
+  } while (0);
+  cleanup();
+  return rc;
+}

@@ -1,0 +1,64 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry
+point include/ga.h declares, and rejects invalid configurations (no GPU
+work is launched here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2208_14961_amd as ga
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "ga.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ga_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 15
+    L = ctypes.CDLL(ga.LIB_PATH)
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_population_words():
+    assert ga.ga_population_words(ga.Config(m=20, n=40000)) == 40000 * 20
+    assert ga.ga_population_words(ga.Config(m=36, n=10)) == 10 * 36 * 2
+    assert ga.ga_population_words(ga.Config(m=64, n=3)) == 3 * 64 * 2
+    assert ga.ga_population_words(ga.Config(m=6, n=3)) == 0
+
+
+@pytest.mark.parametrize("kw", [
+    dict(m=6), dict(m=0), dict(m=68), dict(n=1), dict(n=(1 << 24) + 1), dict(fitness=6),
+    dict(selection=2), dict(tournament_k=0), dict(tournament_k=65), dict(elite=10),
+    dict(xo_threshold=(1 << 32) + 1), dict(mut_threshold=(1 << 32) + 1), dict(nc=0),
+    dict(nr=0), dict(nc=65), dict(flags=2), dict(selection=ga.SEL_PAPER, n=10),
+    dict(selection=ga.SEL_PAPER, n=12, elite=1),
+])
+def test_invalid_configs(kw):
+    base = dict(m=8, n=10)
+    cfg = ga.Config(**{**base, **kw})
+    assert not ga.ga_validate(cfg)
+    assert ga.lib().ga_last_error().decode() != ""
+
+
+def test_valid_configs():
+    for cfg in [ga.Config(m=8, n=10), ga.Config(m=64, n=2, elite=1),
+                ga.Config(m=20, n=40000, fitness=ga.FIT_ABS),
+                ga.Config(m=32, n=200000, elite=2000, fitness=ga.FIT_SQ_PLUS_NNZ),
+                ga.Config(m=12, n=4000, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
+                          xo_threshold=1 << 32, mut_threshold=1 << 32, nc=1, nr=2),
+                ga.Config(m=8, n=10, mut_threshold=0, nc=0, nr=0)]:
+        assert ga.ga_validate(cfg), cfg
+
+
+def test_binding_rejects_host_tensors():
+    import torch
+    cfg = ga.Config(m=8, n=10)
+    with pytest.raises(TypeError):
+        ga.ga_init_population(cfg, torch.zeros((10, 8, 1), dtype=torch.int32))

@@ -1,0 +1,352 @@
+"""GPU-vs-oracle parity of every entry point of libga.  All results are
+integers and must match bit for bit."""
+import numpy as np
+import pytest
+
+import paper_2208_14961_amd as ga
+from oracle import gao
+from tests import hadamard_fixtures as hf
+from tests import inputs
+from tests.gpu_util import (announce, dev_pop_from_int8, empty_keys, empty_pop,
+                            int8_from_dev_pop, keys_np, to_oracle, torch_cuda)
+
+pytestmark = pytest.mark.gpu
+
+ORDERS = list(range(4, 65, 4))
+KINDS = [ga.FIT_SQ, ga.FIT_ABS, ga.FIT_NNZ, ga.FIT_SQ_PLUS_NNZ, ga.FIT_F1, ga.FIT_F2]
+
+
+# --------------------------------------------------------------------------
+# Gram + fitness
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m", ORDERS)
+def test_fitness_random_all_kinds(m):
+    torch = torch_cuda()
+    n = 3 * 256 + 37                       # several blocks and a ragged tail
+    announce("fitness", m, n)
+    pop = inputs.random_population(m, n, seed=100 + m)
+    dpop = dev_pop_from_int8(pop)
+    for kind in KINDS:
+        cfg = ga.Config(m=m, n=n, fitness=kind)
+        keys = empty_keys(cfg)
+        comps = torch.zeros((n, 3), dtype=torch.int32, device="cuda")
+        ga.ga_fitness(cfg, dpop, keys, comps)
+        want, want_c = gao.fitness(to_oracle(cfg), pop, with_comps=True)
+        assert np.array_equal(keys_np(keys), want), kind
+        assert np.array_equal(comps.cpu().numpy().view(np.uint32), want_c)
+        keys2 = empty_keys(cfg)
+        ga.ga_fitness(cfg, dpop, keys2)    # without components
+        assert np.array_equal(keys_np(keys2), want)
+
+
+def test_fitness_known_hadamard_and_census():
+    torch_cuda()
+    for m in hf.ORDERS_WITH_FIXTURE:
+        announce("hadamard fixture", m)
+        H = hf.hadamard(m)
+        # the fixture among random matrices, at a ragged position
+        pop = inputs.random_population(m, 300, seed=m)
+        pop[257] = H
+        cfg = ga.Config(m=m, n=300, fitness=ga.FIT_F2)
+        keys = empty_keys(cfg)
+        ga.ga_fitness(cfg, dev_pop_from_int8(pop), keys)
+        k = keys_np(keys)
+        assert k[257] == 0 and np.count_nonzero(k == 0) >= 1
+        assert np.array_equal(k, gao.fitness(to_oracle(cfg), pop))
+    announce("m4 census")
+    pops = inputs.all_m4_normalized()
+    cfg = ga.Config(m=4, n=len(pops), fitness=ga.FIT_SQ)
+    keys = empty_keys(cfg)
+    ga.ga_fitness(cfg, dev_pop_from_int8(pops), keys)
+    vals, counts = np.unique(keys_np(keys), return_counts=True)
+    assert dict(zip(vals.tolist(), counts.tolist())) == {0: 48, 16: 144, 48: 24}
+
+
+@pytest.mark.parametrize("m", [8, 20, 32, 36, 64])
+def test_fitness_all_equal_columns(m):
+    torch_cuda()
+    announce("all-equal", m)
+    Q = np.ones((m, m), dtype=np.int8)
+    Q[: m // 2, 1:] = -1
+    pop = np.stack([Q] * 5)
+    P = (m - 1) * (m - 2) // 2
+    for kind, want in [(ga.FIT_SQ, P * m * m), (ga.FIT_ABS, P * m), (ga.FIT_NNZ, P),
+                       (ga.FIT_SQ_PLUS_NNZ, P * m * m + P), (ga.FIT_F1, 2 * P * m),
+                       (ga.FIT_F2, 2 * P)]:
+        cfg = ga.Config(m=m, n=5, fitness=kind)
+        keys = empty_keys(cfg)
+        ga.ga_fitness(cfg, dev_pop_from_int8(pop), keys)
+        assert (keys_np(keys) == want).all()
+
+
+# --------------------------------------------------------------------------
+# Initial population
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m", ORDERS)
+def test_init_parity(m):
+    torch_cuda()
+    for n, seed in [(1, 0), (257, 5), (1000, (7 << 32) | 3)]:
+        if n < 2:
+            continue
+        announce("init", m, n, seed)
+        cfg = ga.Config(m=m, n=n, seed=seed)
+        pop = empty_pop(cfg)
+        ga.ga_init_population(cfg, pop)
+        got = int8_from_dev_pop(pop, m)
+        assert np.array_equal(got, gao.init_population(to_oracle(cfg)))
+        assert ga.ga_check_invariants(cfg, pop) == 0
+
+
+# --------------------------------------------------------------------------
+# Steps
+# --------------------------------------------------------------------------
+def _step_chain(cfg: ga.Config, gens: int, start=None):
+    """Runs `gens` steps on the GPU and on the oracle from the same start;
+    compares every generation."""
+    ocfg = to_oracle(cfg)
+    pop = gao.init_population(ocfg) if start is None else start
+    keys = gao.fitness(ocfg, pop)
+    dpop, dkeys = dev_pop_from_int8(pop), empty_keys(cfg)
+    ga.ga_fitness(cfg, dpop, dkeys)
+    assert np.array_equal(keys_np(dkeys), keys)
+    nxt_pop, nxt_keys = empty_pop(cfg), empty_keys(cfg)
+    for g in range(gens):
+        ga.ga_step(cfg, dpop, dkeys, nxt_pop, nxt_keys, g)
+        pop, keys = gao.step(ocfg, pop, keys, g)
+        got = int8_from_dev_pop(nxt_pop, cfg.m)
+        assert np.array_equal(keys_np(nxt_keys), keys), f"keys differ at gen {g + 1}"
+        assert np.array_equal(got, pop), f"population differs at gen {g + 1}"
+        assert ga.ga_check_invariants(cfg, nxt_pop) == 0
+        dpop, nxt_pop = nxt_pop, dpop
+        dkeys, nxt_keys = nxt_keys, dkeys
+
+
+@pytest.mark.parametrize("m", ORDERS)
+def test_step_tournament(m):
+    torch_cuda()
+    n = 2 * 256 + 77
+    announce("step tournament", m, n)
+    cfg = ga.Config(m=m, n=n, seed=m, mut_threshold=ga.rate_threshold(1, 2), nc=2, nr=3)
+    _step_chain(cfg, 3)
+
+
+@pytest.mark.parametrize("m,n,t,elite,kind", [
+    (8, 1024, 2, 0, ga.FIT_SQ),
+    (12, 999, 3, 7, ga.FIT_NNZ),
+    (20, 1001, 1, 0, ga.FIT_ABS),
+    (28, 700, 5, 69, ga.FIT_SQ_PLUS_NNZ),
+    (32, 3000, 2, 30, ga.FIT_SQ_PLUS_NNZ),
+    (44, 513, 4, 100, ga.FIT_F1),
+    (64, 300, 2, 3, ga.FIT_F2),
+])
+def test_step_variants(m, n, t, elite, kind):
+    torch_cuda()
+    announce("step variant", m, n, t, elite, kind)
+    cfg = ga.Config(m=m, n=n, seed=11, tournament_k=t, elite=elite, fitness=kind,
+                    xo_threshold=ga.rate_threshold(3, 4), mut_threshold=ga.rate_threshold(1, 3),
+                    nc=3, nr=2)
+    _step_chain(cfg, 4)
+
+
+def test_step_elite_with_ties():
+    """Many equal keys: the elite set breaks ties by index."""
+    torch_cuda()
+    m, n = 8, 600
+    announce("elite ties", m, n)
+    H = hf.hadamard(8)
+    pop = inputs.random_population(m, n, seed=2)
+    pop[::3] = H                           # 200 copies with key 0
+    cfg = ga.Config(m=m, n=n, seed=4, elite=150, flags=0)
+    _step_chain(cfg, 3, start=pop)
+
+
+@pytest.mark.parametrize("m,N,nc,nr,kind", [
+    (12, 250, 1, 2, ga.FIT_F2), (20, 100, 4, 2, ga.FIT_F1), (16, 1, 2, 2, ga.FIT_F2),
+    (40, 64, 2, 8, ga.FIT_F2), (8, 4096, 3, 2, ga.FIT_F2),
+])
+def test_step_paper_mode(m, N, nc, nr, kind):
+    torch_cuda()
+    announce("step paper", m, N, nc, nr)
+    cfg = ga.Config(m=m, n=4 * N, seed=21, selection=ga.SEL_PAPER, fitness=kind,
+                    xo_threshold=1 << 32, mut_threshold=1 << 32, nc=nc, nr=nr)
+    _step_chain(cfg, 3)
+
+
+# --------------------------------------------------------------------------
+# Whole runs
+# --------------------------------------------------------------------------
+def _run_gpu(cfg: ga.Config):
+    pa, pb = empty_pop(cfg), empty_pop(cfg)
+    ka, kb = empty_keys(cfg), empty_keys(cfg)
+    res = ga.ga_run(cfg, pa, pb, ka, kb)
+    final = pa if res["generation"] % 2 == 0 else pb
+    fk = ka if res["generation"] % 2 == 0 else kb
+    return res, int8_from_dev_pop(final, cfg.m), keys_np(fk)
+
+
+def _same_run(cfg: ga.Config):
+    res, pop, keys = _run_gpu(cfg)
+    want, opop, okeys = gao.run(to_oracle(cfg))
+    for k in ("found", "generation", "index", "best_key"):
+        assert res[k] == want[k], (k, res, want)
+    assert np.array_equal(res["matrix"], opop[want["index"]])
+    assert np.array_equal(pop, opop) and np.array_equal(keys, okeys)
+    return res
+
+
+def test_run_plain_m8_config():
+    """Plain GA, m=8, population 1024, seed 0, SQ, binary tournament,
+    crossover 0.5, one pair flip at rate 0.1, 200 generations, stop at 0."""
+    torch_cuda()
+    announce("run m8 n1024")
+    cfg = ga.Config(m=8, n=1024, seed=0, max_generations=200)
+    res = _same_run(cfg)
+    assert res["found"] and hf.is_hadamard(res["matrix"])
+
+
+@pytest.mark.parametrize("cfg", [
+    ga.Config(m=12, n=600, seed=3, max_generations=40, flags=0),
+    ga.Config(m=4, n=64, seed=1, max_generations=50),
+    ga.Config(m=16, n=2000, seed=5, elite=20, fitness=ga.FIT_SQ_PLUS_NNZ, max_generations=30),
+    ga.Config(m=12, n=400, seed=8, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
+              xo_threshold=1 << 32, mut_threshold=1 << 32, nc=1, nr=2, max_generations=300),
+    ga.Config(m=36, n=300, seed=9, max_generations=6, flags=0),
+    ga.Config(m=8, n=100, seed=0, max_generations=0),
+])
+def test_run_parity(cfg):
+    torch_cuda()
+    announce("run", cfg)
+    _same_run(cfg)
+
+
+# --------------------------------------------------------------------------
+# Batched runs and the server
+# --------------------------------------------------------------------------
+def _mixed_configs():
+    rng = np.random.default_rng(4)
+    out = []
+    for i in range(7):
+        m = int(rng.choice([8, 12, 16, 20, 36, 44]))
+        n = int(rng.integers(100, 1500))
+        out.append(ga.Config(m=m, n=n, seed=4_000_000 + i, max_generations=int(rng.integers(5, 40)),
+                             fitness=int(rng.choice([ga.FIT_SQ, ga.FIT_ABS, ga.FIT_NNZ]))))
+    out.append(ga.Config(m=8, n=256, seed=1, max_generations=100))  # solves early
+    return out
+
+
+def test_run_batch_equals_single_runs():
+    torch_cuda()
+    cfgs = _mixed_configs()
+    announce("batch", len(cfgs))
+    batch = ga.ga_run_batch(cfgs)
+    for cfg, got in zip(cfgs, batch):
+        want, opop, _ = gao.run(to_oracle(cfg))
+        for k in ("found", "generation", "index", "best_key"):
+            assert got[k] == want[k], (cfg, got, want)
+        assert np.array_equal(got["matrix"], opop[want["index"]])
+
+
+def test_server_results_equal_alone_and_mixed():
+    torch_cuda()
+    cfgs = _mixed_configs()
+    announce("server", len(cfgs))
+    srv = ga.Server(hbm_budget_bytes=1 << 30)
+    try:
+        ids = [srv.submit(c) for c in cfgs]
+        mixed = [srv.wait(i) for i in ids]
+        alone = []
+        for c in cfgs:
+            alone.append(srv.wait(srv.submit(c)))
+        for c, a, b in zip(cfgs, mixed, alone):
+            want, opop, _ = gao.run(to_oracle(c))
+            for k in ("found", "generation", "index", "best_key"):
+                assert a[k] == b[k] == want[k]
+            assert np.array_equal(a["matrix"], b["matrix"])
+            assert np.array_equal(a["matrix"], opop[want["index"]])
+        assert all(srv.latency(i) > 0 for i in ids)
+    finally:
+        srv.close()
+
+
+def test_server_small_budget_queues():
+    """A budget that holds only one request at a time still serves all of
+    them, in order, and rejects a request that can never fit."""
+    torch_cuda()
+    cfg = ga.Config(m=20, n=2000, seed=3, max_generations=10, flags=0)
+    one = 2 * (((2000 * 20 * 4) + 255) // 256 * 256) + 2 * (((2000 * 4) + 255) // 256 * 256)
+    announce("server small budget", one)
+    srv = ga.Server(hbm_budget_bytes=one + 100)
+    try:
+        ids = [srv.submit(ga.Config(**{**cfg.__dict__, "seed": s})) for s in range(4)]
+        res = [srv.wait(i) for i in ids]
+        for s, r in zip(range(4), res):
+            want, _, _ = gao.run(to_oracle(ga.Config(**{**cfg.__dict__, "seed": s})))
+            assert r["best_key"] == want["best_key"] and r["index"] == want["index"]
+        big = ga.Config(m=20, n=4000, seed=1, max_generations=1)
+        with pytest.raises(ga.GAError) as e:
+            srv.submit(big)
+        assert e.value.status == ga.GA_EBUDGET
+    finally:
+        srv.close()
+
+
+# --------------------------------------------------------------------------
+# The m=20, population 40,000 workload at full size
+# --------------------------------------------------------------------------
+def test_full_size_m20_n40000_generations():
+    """Full-size check of the m=20, n=40,000 workload in the launch
+    configuration the benchmark times: init, fitness (SQ and ABS keys with
+    components) and the first generations, against the oracle."""
+    torch = torch_cuda()
+    for kind in (ga.FIT_SQ, ga.FIT_ABS):
+        announce("full m20 n40000", kind)
+        cfg = ga.Config(m=20, n=40000, seed=1, fitness=kind, max_generations=500, flags=0)
+        ocfg = to_oracle(cfg)
+        dpop, dkeys = empty_pop(cfg), empty_keys(cfg)
+        comps = torch.zeros((cfg.n, 3), dtype=torch.int32, device="cuda")
+        ga.ga_init_population(cfg, dpop)
+        ga.ga_fitness(cfg, dpop, dkeys, comps)
+        pop = gao.init_population(ocfg)
+        keys, oc = gao.fitness(ocfg, pop, with_comps=True)
+        assert np.array_equal(int8_from_dev_pop(dpop, 20), pop)
+        assert np.array_equal(keys_np(dkeys), keys)
+        assert np.array_equal(comps.cpu().numpy().view(np.uint32), oc)
+        nxt, nk = empty_pop(cfg), empty_keys(cfg)
+        for g in range(2):
+            ga.ga_step(cfg, dpop, dkeys, nxt, nk, g)
+            pop, keys = gao.step(ocfg, pop, keys, g)
+            assert np.array_equal(keys_np(nk), keys)
+            assert np.array_equal(int8_from_dev_pop(nxt, 20), pop)
+            dpop, nxt, dkeys, nk = nxt, dpop, nk, dkeys
+
+
+def test_full_size_m32_n200000_elite_generation():
+    """The m=32, n=200,000 workload with 2,000 elites and key SQ+NNZ:
+    one generation against the oracle."""
+    torch_cuda()
+    announce("full m32 n200000 elite")
+    cfg = ga.Config(m=32, n=200000, seed=2, fitness=ga.FIT_SQ_PLUS_NNZ, elite=2000,
+                    max_generations=1000, flags=0)
+    ocfg = to_oracle(cfg)
+    dpop, dkeys = empty_pop(cfg), empty_keys(cfg)
+    ga.ga_init_population(cfg, dpop)
+    ga.ga_fitness(cfg, dpop, dkeys)
+    pop = gao.init_population(ocfg)
+    keys = gao.fitness(ocfg, pop)
+    assert np.array_equal(keys_np(dkeys), keys)
+    nxt, nk = empty_pop(cfg), empty_keys(cfg)
+    ga.ga_step(cfg, dpop, dkeys, nxt, nk, 0)
+    pop, keys = gao.step(ocfg, pop, keys, 0)
+    assert np.array_equal(keys_np(nk), keys)
+    assert np.array_equal(int8_from_dev_pop(nxt, 32), pop)
+
+
+def test_invalid_configs_rejected():
+    torch_cuda()
+    bad = ga.Config(m=18, n=100)
+    pop = empty_pop(bad)
+    with pytest.raises(ga.GAError) as e:
+        ga.ga_init_population(bad, pop)
+    assert e.value.status == ga.GA_EINVAL
+    with pytest.raises(ga.GAError):
+        ga.ga_run_batch([ga.Config(m=8, n=100, elite=2)])
