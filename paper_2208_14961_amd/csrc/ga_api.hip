@@ -167,7 +167,7 @@ PopDesc make_desc(const ga_config* c, uint32_t* pa, uint32_t* pb,
   d.max_gen = max_gen;
   d.stop_on_found = stop_on_found;
   d.block_begin = 0;
-  d.nblocks = (d.nchild + kBlock - 1) / kBlock;
+  d.nblocks = (d.nchild + kChildBlock - 1) / kChildBlock;
   return d;
 }
 
@@ -194,21 +194,21 @@ static uint32_t select_count(const ga_config* c) {
   return c->elite;
 }
 
-// Enqueues one generation of a single population (the state says which).
+// Enqueues launch `node` of a chunk for a single population: the
+// selection kernels if the mode needs them, then the children kernel.
 static ga_status enqueue_generation(const ga_config* c, const PopDesc& d,
-                                    Workspace* w, hipStream_t s) {
+                                    Workspace* w, uint32_t node,
+                                    hipStream_t s) {
   const uint32_t cnt = select_count(c);
   if (cnt > 0)
-    GA_TRY(launch_select(c, d.pop_a, d.pop_b, d.keys_a, d.keys_b, cnt, w->sel,
-                         d.state, s),
-           "selection kernels");
+    GA_TRY(launch_select(d, cnt, w->sel, node, s), "selection kernels");
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_timing.on) {
     e0 = timing_event();
     e1 = timing_event();
     if (e0 && e1) GA_TRY(hipEventRecord(e0, s), "hipEventRecord");
   }
-  GA_TRY(launch_children_one(d, s), "children kernel");
+  GA_TRY(launch_children_one(d, node, s), "children kernel");
   if (e0 && e1) {
     GA_TRY(hipEventRecord(e1, s), "hipEventRecord");
     g_timing.marks.emplace_back(e0, e1);
@@ -231,7 +231,7 @@ ga_status read_result(const ga_config* c, const RunState& hs,
                              const uint32_t* pop_a, const uint32_t* pop_b,
                              ga_result* out) {
   const uint32_t g = hs.final_gen;
-  const unsigned long long b = hs.best[g & 1u];
+  const unsigned long long b = hs.best;
   out->generation = g;
   out->best_key = (uint32_t)(b >> 32);
   out->index = (uint32_t)(b & 0xffffffffu);
@@ -312,7 +312,7 @@ ga_status ga_step(const ga_config* cfg, const uint32_t* pop_in,
                         odd ? keys_out : ki, odd ? ki : keys_out, w->state,
                         0xffffffffu, 0);
   GA_TRY(launch_set_state(w->state, gen_in, s), "state kernel");
-  return enqueue_generation(cfg, d, w, s);
+  return enqueue_generation(cfg, d, w, 0, s);
 }
 
 ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
@@ -336,18 +336,15 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
   GA_TRY(launch_init(cfg, pop_a, s), "init kernel");
   GA_TRY(launch_fitness(cfg, pop_a, keys_a, nullptr, w->state, s),
          "fitness kernel");
-  GA_TRY(launch_gen0_finish(w->state, stop_on_found, cfg->max_generations, s),
-         "state kernel");
-  // Generations run in chunks: one captured graph of `chunk` generations,
-  // replayed; its kernels read the generation number from the run state and
-  // return at once after the run has stopped.  The host reads the state of
-  // chunk k while chunk k+1 runs.
+  // Generations run in chunks: one captured graph of `chunk` launches and
+  // the gen_base advance, replayed.  The host reads the state of chunk k
+  // while chunk k+1 runs; launches past the end of the run return at once.
   const uint32_t chunk = std::min<uint32_t>(64, std::max<uint32_t>(1, cfg->max_generations));
   const uint32_t nchunks = (cfg->max_generations + chunk - 1) / chunk;
   if (g_timing.on) {
     // measurement mode: direct launches, each children kernel timed
     for (uint32_t i = 0; i < cfg->max_generations; ++i) {
-      st = enqueue_generation(cfg, d, w, s);
+      st = enqueue_generation(cfg, d, w, i, s);
       if (st != GA_OK) return st;
     }
   } else if (nchunks > 0) {
@@ -363,7 +360,10 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
       GA_TRY(hipStreamBeginCapture(w->capture, hipStreamCaptureModeThreadLocal),
              "hipStreamBeginCapture");
       for (uint32_t i = 0; i < chunk && st == GA_OK; ++i)
-        st = enqueue_generation(cfg, d, w, w->capture);
+        st = enqueue_generation(cfg, d, w, i, w->capture);
+      if (st == GA_OK)
+        st = hip_status(launch_advance_one(w->state, chunk, w->capture),
+                        "advance kernel");
       hipError_t ce = hipStreamEndCapture(w->capture, &g);
       if (st != GA_OK) return st;
       GA_TRY(ce, "hipStreamEndCapture");
@@ -391,21 +391,19 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
         if (st != GA_OK) return st;
       }
       GA_TRY(hipEventSynchronize(w->ev[k & 1]), "hipEventSynchronize");
-      if (w->host_state[k & 1].stop) break;
+      if (run_done(w->host_state[k & 1], cfg->max_generations, stop_on_found))
+        break;
     }
     // s continues after everything the capture stream did
     GA_TRY(hipEventRecord(w->ev[2], w->capture), "hipEventRecord");
     GA_TRY(hipStreamWaitEvent(s, w->ev[2], 0), "hipStreamWaitEvent");
   }
+  GA_TRY(launch_finish_one(d, s), "finish kernel");
   GA_TRY(hipMemcpyAsync(w->host_state, w->state, sizeof(RunState),
                         hipMemcpyDeviceToHost, s),
          "hipMemcpyAsync(state)");
   GA_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
   RunState hs = *w->host_state;
-  if (!hs.stop) {
-    set_error("run did not reach its stop condition");
-    return GA_EDEVICE;
-  }
   return read_result(cfg, hs, pop_a, pop_b, out);
 }
 

@@ -54,7 +54,21 @@ __device__ __forceinline__ Parents pick_parents(const PopDesc& d, uint32_t G,
   return r;
 }
 
+// The four 32-bit words of a lane's Philox block, swapped with lane ^ 1.
+__device__ __forceinline__ U4 shfl_xor1(const U4& v) {
+  return U4{(uint32_t)__shfl_xor((int)v.x, 1, 64),
+            (uint32_t)__shfl_xor((int)v.y, 1, 64),
+            (uint32_t)__shfl_xor((int)v.z, 1, 64),
+            (uint32_t)__shfl_xor((int)v.w, 1, 64)};
+}
+
 // Orders up to 32: the child lives in registers from crossover to store.
+// The two children of a pair sit in lanes q and q ^ 1 of one wave: for
+// binary tournaments each computes one of the pair's two Philox blocks
+// (selection, crossover) and one tournament, and they swap the results.
+// All draws come before the dependent loads, so their latency overlaps the
+// arithmetic.  Lanes past the last child compute a copy of the last pair
+// and store nothing.
 template <int M>
 __device__ __forceinline__ unsigned long long child(const PopDesc& d,
                                                    uint32_t G, uint32_t q) {
@@ -64,19 +78,87 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d,
   const uint32_t* kin = odd_in ? d.keys_b : d.keys_a;
   uint32_t* pout = odd_in ? d.pop_a : d.pop_b;
   uint32_t* kout = odd_in ? d.keys_a : d.keys_b;
-  const uint32_t p = q >> 1, c = q & 1u;
-  const Parents par = pick_parents(d, G, q, MW, pin, kin, pout);
-  const U4 xo = draw_block(d.seed, kStreamXover, G, p, 0);
+  const bool valid = q < d.nchild;
+  const uint32_t npairs = (d.nchild + 1) >> 1;
+  const uint32_t p = min(q >> 1, npairs - 1), c = q & 1u;
+  const bool binary = !d.paper && d.t == 2;  // uniform over the launch
+  U4 xo, sel;
+  if (binary) {
+    const U4 mine = draw_block(d.seed, c ? kStreamXover : kStreamSelect, G, p, 0);
+    const U4 other = shfl_xor1(mine);
+    sel = c ? other : mine;
+    xo = c ? mine : other;
+  } else {
+    xo = draw_block(d.seed, kStreamXover, G, p, 0);
+    sel = xo;
+  }
+  const bool mut = (uint64_t)(c ? xo.w : xo.z) < d.mut_thr;
   const uint32_t cut =
       ((uint64_t)xo.x < d.xo_thr) ? 1u + bounded(xo.y, M - 1) : (uint32_t)M;
+  // first mutation block, drawn before the loads
+  U4 mb0 = U4{0, 0, 0, 0};
+  if (mut) mb0 = draw_block(d.seed, kStreamMutate, G, q, 0);
+  // parents
+  const uint32_t* A;
+  const uint32_t* B;
+  uint32_t dst;
+  if (binary) {
+    const uint32_t x0 = bounded(c ? sel.z : sel.x, d.n);
+    const uint32_t x1 = bounded(c ? sel.w : sel.y, d.n);
+    const uint32_t k0 = kin[x0], k1 = kin[x1];
+    const uint32_t w = (k1 < k0 || (k1 == k0 && x1 < x0)) ? x1 : x0;
+    const uint32_t wo = (uint32_t)__shfl_xor((int)w, 1, 64);
+    A = pin + (size_t)(c ? wo : w) * MW;
+    B = pin + (size_t)(c ? w : wo) * MW;
+    dst = d.elite + q;
+  } else {
+    const Parents par = pick_parents(d, G, 2 * p + c, MW, pin, kin, pout);
+    A = par.A;
+    B = par.B;
+    dst = par.dst;
+  }
+  const uint32_t* first = c ? B : A;
+  const uint32_t* second = c ? A : B;
+  // mutation (Sec. 3.5): up to four columns by flip masks computed from the
+  // parents' words, applied while crossing over; more columns use the
+  // general in-register path
+  uint32_t mcol[4] = {0, 0, 0, 0}, mmask[4] = {0, 0, 0, 0};
+  const bool fast = d.nc <= 4;
+  if (mut && fast) {
+    DrawSeq ds(d.seed, kStreamMutate, G, q, mb0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if ((uint32_t)k < d.nc) {
+        const uint32_t col = 1u + bounded(ds.at(k), M - 1);
+        uint32_t v = ((col < cut) ? first : second)[col];
+#pragma unroll
+        for (int kp = 0; kp < k; ++kp)
+          if (mcol[kp] == col) v ^= mmask[kp];
+        uint32_t mask = 0;
+        for (uint32_t ir = 0; ir < d.nr; ++ir) {
+          const uint32_t r1 = bounded(ds.at(d.nc + 2 * ir), M);
+          const uint32_t r2 = bounded(ds.at(d.nc + 2 * ir + 1), M);
+          const uint32_t x = v ^ mask;
+          if (((x >> r1) ^ (x >> r2)) & 1u) mask ^= (1u << r1) | (1u << r2);
+        }
+        mcol[k] = col;
+        mmask[k] = mask;
+      }
+    }
+  }
   Cols<M> cols;
-  load_crossed<M>(c ? par.B : par.A, c ? par.A : par.B, cut, cols);
-  if ((uint64_t)(c ? xo.w : xo.z) < d.mut_thr)
-    mutate<M>(cols, d.seed, G, q, d.nc, d.nr);
+  load_crossed<M>(first, second, cut, cols);
+  if (mut) {
+    if (fast)
+      apply_masks<M>(cols, d.nc, mcol, mmask);
+    else
+      mutate<M>(cols, d.seed, G, q, d.nc, d.nr);
+  }
   const uint32_t key = fitness<M>(cols, d.kind, false, nullptr);
-  store_cols<M>(pout + (size_t)par.dst * MW, cols);
-  kout[par.dst] = key;
-  return ((unsigned long long)key << 32) | par.dst;
+  if (!valid) return ~0ull;
+  store_cols<M>(pout + (size_t)dst * MW, cols);
+  kout[dst] = key;
+  return ((unsigned long long)key << 32) | dst;
 }
 
 // Orders 36..64 (two words per column, runtime order): crossover copies the
@@ -84,6 +166,7 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d,
 // reads them back in register tiles.
 __device__ __forceinline__ unsigned long long child_w2(const PopDesc& d,
                                                        uint32_t G, uint32_t q) {
+  if (q >= d.nchild) return ~0ull;
   const uint32_t M = d.m, MW = 2 * M;
   const bool odd_in = ((G - 1) & 1u) != 0;
   const uint32_t* pin = odd_in ? d.pop_b : d.pop_a;
@@ -128,50 +211,43 @@ __device__ __forceinline__ unsigned long long child_w2(const PopDesc& d,
   return ((unsigned long long)key << 32) | par.dst;
 }
 
-// The block's children, then the per-population generation close-out.
+// Generation G of launch `node`, and whether it runs (see RunState).
+__device__ __forceinline__ bool generation_of(const PopDesc& d, uint32_t node,
+                                              uint32_t* G) {
+  const RunState* st = d.state;
+  *G = __hip_atomic_load(&st->gen_base, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT) + node + 1;
+  if (*G > d.max_gen) return false;
+  if (d.stop_on_found &&
+      __hip_atomic_load(&st->found_gen, __ATOMIC_RELAXED,
+                        __HIP_MEMORY_SCOPE_AGENT) < *G)
+    return false;
+  return true;
+}
+
+// The block's children (one wave); a wave holding a key of 0 records it.
 template <typename F>
-__device__ __forceinline__ void children_block(const PopDesc& d, F&& body) {
-  RunState* st = d.state;
-  if (ld_acq(&st->stop)) return;  // uniform over the block
-  const uint32_t G = ld_acq(&st->gen) + 1;
-  const uint32_t q = (blockIdx.x - d.block_begin) * kBlock + threadIdx.x;
-  unsigned long long best = ~0ull;
-  if (q < d.nchild) best = body(G, q);
-  best = block_min_u64(best);
-  if (threadIdx.x == 0) {
-    atomicMin(&st->best[G & 1u], best);
-    __threadfence();
-    const uint32_t done = atomicAdd(&st->blocks_done, 1u);
-    if (done == d.nblocks - 1) {
-      // last block of this population: the generation is complete
-      __threadfence();
-      const unsigned long long b = __hip_atomic_load(
-          &st->best[G & 1u], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      const uint32_t key = (uint32_t)(b >> 32);
-      st->best[(G + 1) & 1u] = ~0ull;
-      st->blocks_done = 0;
-      if ((d.stop_on_found && key == 0) || G >= d.max_gen) {
-        st->final_gen = G;
-        __hip_atomic_store(&st->stop, 1u, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      }
-      __hip_atomic_store(&st->gen, G, __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+__device__ __forceinline__ void children_block(const PopDesc& d, uint32_t node,
+                                               F&& body) {
+  uint32_t G;
+  if (!generation_of(d, node, &G)) return;  // uniform over the launch
+  const uint32_t q = (blockIdx.x - d.block_begin) * kChildBlock + threadIdx.x;
+  note_zero(d.state, body(G, q), G);
 }
 
 // One population, order M <= 32, descriptor by value.
 template <int M>
-__global__ __launch_bounds__(kBlock) void children_one_kernel(PopDesc d) {
-  children_block(d, [&](uint32_t G, uint32_t q) __attribute__((always_inline)) {
+__global__ __launch_bounds__(kChildBlock) void children_one_kernel(PopDesc d,
+                                                                   uint32_t node) {
+  children_block(d, node, [&](uint32_t G, uint32_t q) __attribute__((always_inline)) {
     return child<M>(d, G, q);
   });
 }
 
 // One population, order 36..64.
-__global__ __launch_bounds__(kBlock) void children_one_w2_kernel(PopDesc d) {
-  children_block(d, [&](uint32_t G, uint32_t q) __attribute__((always_inline)) {
+__global__ __launch_bounds__(kChildBlock) void children_one_w2_kernel(
+    PopDesc d, uint32_t node) {
+  children_block(d, node, [&](uint32_t G, uint32_t q) __attribute__((always_inline)) {
     return child_w2(d, G, q);
   });
 }
@@ -183,56 +259,59 @@ __global__ __launch_bounds__(kBlock) void children_one_w2_kernel(PopDesc d) {
 // branch, and the long branches it then emits reuse the return-address
 // registers, so the function never returns.
 template <int M>
-__global__ __launch_bounds__(kBlock) void children_multi_kernel(
-    const PopDesc* __restrict__ descs, const uint32_t* __restrict__ block_pop) {
+__global__ __launch_bounds__(kChildBlock) void children_multi_kernel(
+    const PopDesc* __restrict__ descs, const uint32_t* __restrict__ block_pop,
+    uint32_t node) {
   const PopDesc d = descs[block_pop[blockIdx.x]];
-  children_block(d, [&](uint32_t G, uint32_t q) __attribute__((always_inline)) {
+  children_block(d, node, [&](uint32_t G, uint32_t q) __attribute__((always_inline)) {
     return child<M>(d, G, q);
   });
 }
 
 // Several populations of orders 36..64 in one launch.
-__global__ __launch_bounds__(kBlock) void children_multi_w2_kernel(
-    const PopDesc* __restrict__ descs, const uint32_t* __restrict__ block_pop) {
+__global__ __launch_bounds__(kChildBlock) void children_multi_w2_kernel(
+    const PopDesc* __restrict__ descs, const uint32_t* __restrict__ block_pop,
+    uint32_t node) {
   const PopDesc d = descs[block_pop[blockIdx.x]];
-  children_block(d, [&](uint32_t G, uint32_t q) __attribute__((always_inline)) {
+  children_block(d, node, [&](uint32_t G, uint32_t q) __attribute__((always_inline)) {
     return child_w2(d, G, q);
   });
 }
 
 hipError_t launch_children(const PopDesc* descs_dev, const uint32_t* block_pop,
-                           uint32_t total_blocks, uint32_t m, hipStream_t s) {
+                           uint32_t total_blocks, uint32_t m, uint32_t node,
+                           hipStream_t s) {
   if (total_blocks == 0) return hipSuccess;
-  const dim3 grid(total_blocks), block(kBlock);
+  const dim3 grid(total_blocks), block(kChildBlock);
   switch (m) {
 #define GA_MULTI_CASE(MM)                                                    \
   case MM:                                                                   \
     hipLaunchKernelGGL(children_multi_kernel<MM>, grid, block, 0, s,         \
-                       descs_dev, block_pop);                                \
+                       descs_dev, block_pop, node);                          \
     break;
     GA_MULTI_CASE(4) GA_MULTI_CASE(8) GA_MULTI_CASE(12) GA_MULTI_CASE(16)
     GA_MULTI_CASE(20) GA_MULTI_CASE(24) GA_MULTI_CASE(28) GA_MULTI_CASE(32)
 #undef GA_MULTI_CASE
     default:
       hipLaunchKernelGGL(children_multi_w2_kernel, grid, block, 0, s,
-                         descs_dev, block_pop);
+                         descs_dev, block_pop, node);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_children_one(const PopDesc& d, hipStream_t s) {
+hipError_t launch_children_one(const PopDesc& d, uint32_t node, hipStream_t s) {
   if (d.nblocks == 0) return hipSuccess;
-  const dim3 grid(d.nblocks), block(kBlock);
+  const dim3 grid(d.nblocks), block(kChildBlock);
   switch (d.m) {
 #define GA_CH_CASE(MM)                                                      \
   case MM:                                                                  \
-    hipLaunchKernelGGL(children_one_kernel<MM>, grid, block, 0, s, d);      \
+    hipLaunchKernelGGL(children_one_kernel<MM>, grid, block, 0, s, d, node);\
     break;
     GA_CH_CASE(4) GA_CH_CASE(8) GA_CH_CASE(12) GA_CH_CASE(16)
     GA_CH_CASE(20) GA_CH_CASE(24) GA_CH_CASE(28) GA_CH_CASE(32)
 #undef GA_CH_CASE
     default:
-      hipLaunchKernelGGL(children_one_w2_kernel, grid, block, 0, s, d);
+      hipLaunchKernelGGL(children_one_w2_kernel, grid, block, 0, s, d, node);
   }
   return hipGetLastError();
 }

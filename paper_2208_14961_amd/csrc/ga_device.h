@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 namespace ga {
 
 // Philox stream tags (the "stream" word of the counter).
@@ -96,6 +98,9 @@ struct DrawSeq {
   U4 cur;
   __device__ DrawSeq(uint64_t s, uint32_t st, uint32_t g, uint32_t i)
       : seed(s), stream(st), gen(g), idx(i), blk(0xffffffffu) {}
+  // starts with block 0 already computed
+  __device__ DrawSeq(uint64_t s, uint32_t st, uint32_t g, uint32_t i, U4 b0)
+      : seed(s), stream(st), gen(g), idx(i), blk(0), cur(b0) {}
   __device__ uint32_t at(uint32_t d) {
     const uint32_t b = d >> 2;
     if (b != blk) {
@@ -342,49 +347,65 @@ __device__ __forceinline__ void load_crossed(const uint32_t* first,
   }
 }
 
-// Column `col` (runtime) of a register-resident individual as 64 bits.
-template <int M>
-__device__ __forceinline__ uint64_t get_col(const Cols<M>& c, uint32_t col) {
-  constexpr int W = Cols<M>::W;
-  uint64_t v = 0;
-#pragma unroll
-  for (int j = 1; j < M; ++j) {
-    uint64_t x = c.w[j][0];
-    if (W > 1) x |= (uint64_t)c.w[j][W - 1] << 32;
-    v = ((uint32_t)j == col) ? x : v;
-  }
-  return v;
+// (a == J) ? x : 0, with the comparison kept opaque to the compiler: a
+// column chosen at run time is then updated by a select per column instead
+// of the indexed scratch access the compiler would otherwise emit.
+template <int J>
+__device__ __forceinline__ uint32_t pick_if_eq(uint32_t a, uint32_t x) {
+  uint32_t r;
+  asm("v_cmp_eq_u32 vcc, %2, %1\n\tv_cndmask_b32 %0, 0, %3, vcc"
+      : "=v"(r)
+      : "v"(a), "n"(J), "v"(x)
+      : "vcc");
+  return r;
 }
 
+// Column-exchange crossover while loading, plus up to four mutation masks:
+// word j = (j < cut ? first : second)[j] ^ sum over k of (col[k] == j ?
+// mask[k] : 0).  Unused mask slots have col = 0, which no column j >= 1
+// matches (column 0 is never mutated).
 template <int M>
-__device__ __forceinline__ void set_col(Cols<M>& c, uint32_t col, uint64_t v) {
-  constexpr int W = Cols<M>::W;
+__device__ __forceinline__ void apply_masks(Cols<M>& c, uint32_t nmask,
+                                            const uint32_t (&col)[4],
+                                            const uint32_t (&mask)[4]) {
+  static_assert(M <= 32, "register path holds one word per column");
 #pragma unroll
-  for (int j = 1; j < M; ++j) {
-    if ((uint32_t)j == col) {
-      c.w[j][0] = (uint32_t)v;
-      if (W > 1) c.w[j][W - 1] = (uint32_t)(v >> 32);
+  for (int k = 0; k < 4; ++k) {
+    if ((uint32_t)k < nmask) {
+      // compile-time column indices: each j is its own register
+      [&]<int... J>(std::integer_sequence<int, J...>) __attribute__((always_inline)) {
+        ((c.w[J + 1][0] ^= pick_if_eq<J + 1>(col[k], mask[k])), ...);
+      }(std::make_integer_sequence<int, M - 1>{});
     }
   }
 }
 
 // Pair-flip mutation (Sec. 3.5, third method) of child ordinal q in
-// generation G: nc columns, nr row pairs shared by the columns; a pair is
-// negated only when its two entries differ, so the column stays balanced.
+// generation G, register-resident (M <= 32), any number of columns: nc
+// columns, nr row pairs shared by the columns; a pair is negated only when
+// its two entries differ, so the column stays balanced.  The column is read
+// and written back through per-column selects (no indexed access).
 template <int M>
 __device__ __forceinline__ void mutate(Cols<M>& c, uint64_t seed, uint32_t G,
                                        uint32_t q, uint32_t nc, uint32_t nr) {
+  static_assert(M <= 32, "register path holds one word per column");
   DrawSeq ds(seed, kStreamMutate, G, q);
   for (uint32_t jc = 0; jc < nc; ++jc) {
     const uint32_t col = 1u + bounded(ds.at(jc), M - 1);
-    uint64_t v = get_col<M>(c, col);
+    uint32_t v = 0;
+    [&]<int... J>(std::integer_sequence<int, J...>) __attribute__((always_inline)) {
+      ((v |= pick_if_eq<J + 1>(col, c.w[J + 1][0])), ...);
+    }(std::make_integer_sequence<int, M - 1>{});
+    uint32_t mask = 0;
     for (uint32_t ir = 0; ir < nr; ++ir) {
       const uint32_t r1 = bounded(ds.at(nc + 2 * ir), M);
       const uint32_t r2 = bounded(ds.at(nc + 2 * ir + 1), M);
-      const uint64_t b1 = (v >> r1) & 1ull, b2 = (v >> r2) & 1ull;
-      if (b1 != b2) v ^= (1ull << r1) | (1ull << r2);
+      const uint32_t x = v ^ mask;
+      if (((x >> r1) ^ (x >> r2)) & 1u) mask ^= (1u << r1) | (1u << r2);
     }
-    set_col<M>(c, col, v);
+    [&]<int... J>(std::integer_sequence<int, J...>) __attribute__((always_inline)) {
+      ((c.w[J + 1][0] ^= pick_if_eq<J + 1>(col, mask)), ...);
+    }(std::make_integer_sequence<int, M - 1>{});
   }
 }
 

@@ -11,20 +11,30 @@ namespace ga {
 constexpr uint32_t kMaxN = 1u << 24;        // population size limit
 constexpr uint32_t kMaxElite = 1u << 16;    // elite count limit
 constexpr uint32_t kKeyBits = 24;           // selection ranks keys < 2^24
-constexpr int kBlock = 256;                 // threads per block, step kernels
+constexpr int kBlock = 256;                 // threads per block, bulk kernels
+constexpr int kChildBlock = 64;             // one wave per block: children
 constexpr int kSelTile = 2048;              // elements per block, selection
 constexpr int kMaxSelBlocks = 8192;         // kMaxN / kSelTile
 
 // Device-resident progress of one run.  Generation g of the run lives in
-// buffer A if g is even, B if odd.
+// buffer A if g is even, B if odd.  Launches are issued in chunks: launch i
+// of a chunk (its "node") produces generation G = gen_base + i + 1, and a
+// small kernel after the chunk advances gen_base.  A generation runs only if
+// G <= max_gen and, when stopping on a solution, no earlier generation held
+// a key of 0.  No per-block fences or counters are needed: each kernel
+// boundary orders the generations.
 struct RunState {
-  unsigned long long best[2];  // min (key << 32 | slot) of gens of parity 0/1
-  uint32_t gen;                // last completed generation
-  uint32_t stop;               // 1 once the run is over
-  uint32_t final_gen;          // generation reported when stopped
-  uint32_t blocks_done;        // last-block detection of the step kernel
-  uint32_t pad[2];
+  unsigned long long best;  // (key << 32 | slot) of the reported generation
+  uint32_t gen_base;        // generations completed before the current chunk
+  uint32_t found_gen;       // first generation holding a key of 0, or ~0u
+  uint32_t final_gen;       // reported generation (set by the finish kernel)
+  uint32_t pad[3];
 };
+
+// Host-side view: has the run finished after the chunks launched so far?
+inline bool run_done(const RunState& s, uint32_t max_gen, bool stop_on_found) {
+  return s.gen_base >= max_gen || (stop_on_found && s.found_gen <= s.gen_base);
+}
 
 // One population in a step launch.
 struct PopDesc {
@@ -58,28 +68,36 @@ struct SelWork {
   uint32_t cnt[4];                // last-block counters
 };
 
-// ---- launchers (ga_kernels.hip) ----------------------------------------
+// ---- launchers (ga_kernels.hip, ga_children.hip, ga_select.hip) ---------
 hipError_t launch_init(const ga_config* c, uint32_t* pop, hipStream_t s);
-// keys for all n; comps nullable; st nullable (then no best tracking)
+// keys for all n; comps nullable; st nullable, else a key of 0 in generation
+// 0 sets st->found_gen = 0
 hipError_t launch_fitness(const ga_config* c, const uint32_t* pop,
                           uint32_t* keys, uint32_t* comps, RunState* st,
                           hipStream_t s);
-// selection of the `count` smallest (key, index) of generation g (read from
-// the state) into generation g + 1 (elitism: slot = rank in index order;
-// paper mode: slot = pi^-1(rank)); buffers by parity as in RunState
-hipError_t launch_select(const ga_config* c, uint32_t* pop_a, uint32_t* pop_b,
-                         uint32_t* keys_a, uint32_t* keys_b, uint32_t count,
-                         SelWork* ws, RunState* st, hipStream_t s);
+// selection of the `count` smallest (key, index) of generation G - 1 into
+// generation G (elitism: slot = rank in index order; paper mode: slot =
+// pi^-1(rank)), G from the state and the launch's node
+hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
+                         uint32_t node, hipStream_t s);
 // children of every population in descs (device array); all of order m if
 // m <= 32, else all of orders 36..64
 hipError_t launch_children(const PopDesc* descs_dev, const uint32_t* block_pop,
-                           uint32_t total_blocks, uint32_t m, hipStream_t s);
+                           uint32_t total_blocks, uint32_t m, uint32_t node,
+                           hipStream_t s);
 // children of one population (descriptor passed by value)
-hipError_t launch_children_one(const PopDesc& d, hipStream_t s);
-hipError_t launch_set_state(RunState* st, uint32_t gen, hipStream_t s);
-hipError_t launch_gen0_finish(RunState* st, uint32_t stop_on_found,
-                              uint32_t max_gen, hipStream_t s);
+hipError_t launch_children_one(const PopDesc& d, uint32_t node, hipStream_t s);
+// gen_base += k for every population of the table
+hipError_t launch_advance(const PopDesc* descs_dev, uint32_t ndesc, uint32_t k,
+                          hipStream_t s);
+hipError_t launch_advance_one(RunState* st, uint32_t k, hipStream_t s);
+// final generation of every population of the table and its best (key, slot)
+hipError_t launch_finish(const PopDesc* descs_dev, uint32_t ndesc,
+                         hipStream_t s);
+hipError_t launch_finish_one(const PopDesc& d, hipStream_t s);
 hipError_t launch_reset_state(RunState* st, hipStream_t s);
+// state for a single step from generation gen (no stop condition)
+hipError_t launch_set_state(RunState* st, uint32_t gen, hipStream_t s);
 hipError_t launch_check(const ga_config* c, const uint32_t* pop,
                         uint32_t* bad, hipStream_t s);
 
@@ -121,11 +139,14 @@ class MultiLaunch {
   ~MultiLaunch();
   // descs: one per run (state pointers set); rebuilds and uploads the tables
   ga_status set(const PopDesc* descs, uint32_t count, hipStream_t s);
-  // one generation of every run that has not stopped
-  ga_status enqueue_generation(hipStream_t s);
-  // `gens` generations as one graph launch on s (captured on first use
-  // after set(); s must not be the null stream)
+  // launch `node` of a chunk: one generation of every run still going
+  ga_status enqueue_generation(uint32_t node, hipStream_t s);
+  // a chunk of `gens` launches and the gen_base advance, as one graph
+  // launch on s (captured on first use after set(); s must not be the null
+  // stream)
   ga_status launch_chunk(uint32_t gens, hipStream_t s);
+  // the reported generation and best (key, slot) of every run
+  ga_status finish(hipStream_t s);
 
  private:
   struct Group {
@@ -133,12 +154,14 @@ class MultiLaunch {
     PopDesc* desc = nullptr;
     uint32_t* map = nullptr;
     size_t cap_desc = 0, cap_map = 0;
-    uint32_t nblocks = 0;
+    uint32_t ndesc = 0, nblocks = 0;
   };
   Group groups_[9];                  // orders 4..32 step 4, then 36..64
   hipGraphExec_t graph_ = nullptr;
   uint32_t graph_gens_ = 0;
   hipStream_t capture_ = nullptr;
+  hipStream_t branch_[9] = {};       // capture branches, one per group
+  hipEvent_t fork_[10] = {};         // join events per group, fork event
 };
 
 }  // namespace ga

@@ -65,7 +65,7 @@ __device__ __forceinline__ void fitness_epilogue(uint32_t k, uint32_t key,
 }
 
 template <int M>
-__global__ __launch_bounds__(kBlock) void fitness_kernel(
+__global__ __launch_bounds__(kChildBlock) void fitness_kernel(
     const uint32_t* __restrict__ pop, uint32_t n, uint32_t kind,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ comps, RunState* st) {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -77,13 +77,10 @@ __global__ __launch_bounds__(kBlock) void fitness_kernel(
     const uint32_t key = fitness<M>(c, kind, comps != nullptr, out3);
     fitness_epilogue(k, key, out3, keys, comps, &best);
   }
-  if (st) {
-    best = block_min_u64(best);
-    if (threadIdx.x == 0) atomicMin(&st->best[0], best);
-  }
+  if (st) note_zero(st, best, 0);
 }
 
-__global__ __launch_bounds__(kBlock) void fitness_kernel_w2(
+__global__ __launch_bounds__(kChildBlock) void fitness_kernel_w2(
     const uint32_t* __restrict__ pop, uint32_t n, uint32_t m, uint32_t kind,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ comps, RunState* st) {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -94,38 +91,62 @@ __global__ __launch_bounds__(kBlock) void fitness_kernel_w2(
         fitness_w2(pop + (size_t)k * 2 * m, m, kind, comps != nullptr, out3);
     fitness_epilogue(k, key, out3, keys, comps, &best);
   }
-  if (st) {
-    best = block_min_u64(best);
-    if (threadIdx.x == 0) atomicMin(&st->best[0], best);
-  }
+  if (st) note_zero(st, best, 0);
 }
 
 __global__ void reset_state_kernel(RunState* st) {
-  st->best[0] = ~0ull;
-  st->best[1] = ~0ull;
-  st->gen = 0;
-  st->stop = 0;
+  st->best = ~0ull;
+  st->gen_base = 0;
+  st->found_gen = ~0u;
   st->final_gen = 0;
-  st->blocks_done = 0;
-}
-
-__global__ void gen0_finish_kernel(RunState* st, uint32_t stop_on_found,
-                                   uint32_t max_gen) {
-  const uint32_t key = (uint32_t)(st->best[0] >> 32);
-  st->gen = 0;
-  st->best[1] = ~0ull;
-  if ((stop_on_found && key == 0) || max_gen == 0) {
-    st->final_gen = 0;
-    st->stop = 1;
-  }
 }
 
 __global__ void set_state_kernel(RunState* st, uint32_t gen) {
-  st->gen = gen;
-  st->stop = 0;
-  st->final_gen = 0;
-  st->blocks_done = 0;
-  st->best[(gen + 1) & 1u] = ~0ull;
+  st->best = ~0ull;
+  st->gen_base = gen;
+  st->found_gen = ~0u;
+  st->final_gen = gen + 1;
+}
+
+// gen_base += k for the runs of a launch table (one thread per run) or one
+// run.
+__global__ void advance_kernel(const PopDesc* __restrict__ descs, uint32_t ndesc,
+                               uint32_t k) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ndesc) descs[i].state->gen_base += k;
+}
+
+__global__ void advance_one_kernel(RunState* st, uint32_t k) {
+  st->gen_base += k;
+}
+
+// The reported generation of a run (the first one holding a key of 0 when
+// stopping on a solution, else the last one) and its best (key, slot), the
+// lowest slot among equal keys.  One block per run.
+__device__ __forceinline__ void finish_run(const PopDesc& d) {
+  RunState* st = d.state;
+  const uint32_t found = st->found_gen;
+  const uint32_t g = (d.stop_on_found && found <= d.max_gen) ? found : d.max_gen;
+  const uint32_t* keys = (g & 1u) ? d.keys_b : d.keys_a;
+  unsigned long long best = ~0ull;
+  for (uint32_t i = threadIdx.x; i < d.n; i += kBlock) {
+    const unsigned long long v = ((unsigned long long)keys[i] << 32) | i;
+    best = v < best ? v : best;
+  }
+  best = block_min_u64(best);
+  if (threadIdx.x == 0) {
+    st->best = best;
+    st->final_gen = g;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void finish_kernel(
+    const PopDesc* __restrict__ descs) {
+  finish_run(descs[blockIdx.x]);
+}
+
+__global__ __launch_bounds__(kBlock) void finish_one_kernel(PopDesc d) {
+  finish_run(d);
 }
 
 // ---------------------------------------------------------------------------
@@ -189,16 +210,16 @@ hipError_t launch_init(const ga_config* c, uint32_t* pop, hipStream_t s) {
 hipError_t launch_fitness(const ga_config* c, const uint32_t* pop,
                           uint32_t* keys, uint32_t* comps, RunState* st,
                           hipStream_t s) {
-  const uint32_t grid = cdiv(c->n, kBlock);
+  const uint32_t grid = cdiv(c->n, kChildBlock);
   if (c->m > 32) {
-    hipLaunchKernelGGL(fitness_kernel_w2, dim3(grid), dim3(kBlock), 0, s, pop,
+    hipLaunchKernelGGL(fitness_kernel_w2, dim3(grid), dim3(kChildBlock), 0, s, pop,
                        c->n, c->m, c->fitness, keys, comps, st);
     return hipGetLastError();
   }
   switch (c->m) {
 #define GA_FIT_CASE(MM)                                                       \
   case MM:                                                                    \
-    hipLaunchKernelGGL(fitness_kernel<MM>, dim3(grid), dim3(kBlock), 0, s,    \
+    hipLaunchKernelGGL(fitness_kernel<MM>, dim3(grid), dim3(kChildBlock), 0, s, \
                        pop, c->n, c->fitness, keys, comps, st);              \
     break;
     GA_FIT_CASE(4) GA_FIT_CASE(8) GA_FIT_CASE(12) GA_FIT_CASE(16)
@@ -214,15 +235,33 @@ hipError_t launch_reset_state(RunState* st, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_gen0_finish(RunState* st, uint32_t stop_on_found,
-                              uint32_t max_gen, hipStream_t s) {
-  hipLaunchKernelGGL(gen0_finish_kernel, dim3(1), dim3(1), 0, s, st,
-                     stop_on_found, max_gen);
+hipError_t launch_set_state(RunState* st, uint32_t gen, hipStream_t s) {
+  hipLaunchKernelGGL(set_state_kernel, dim3(1), dim3(1), 0, s, st, gen);
   return hipGetLastError();
 }
 
-hipError_t launch_set_state(RunState* st, uint32_t gen, hipStream_t s) {
-  hipLaunchKernelGGL(set_state_kernel, dim3(1), dim3(1), 0, s, st, gen);
+hipError_t launch_advance(const PopDesc* descs_dev, uint32_t ndesc, uint32_t k,
+                          hipStream_t s) {
+  if (ndesc == 0) return hipSuccess;
+  hipLaunchKernelGGL(advance_kernel, dim3(cdiv(ndesc, kBlock)), dim3(kBlock),
+                     0, s, descs_dev, ndesc, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_one(RunState* st, uint32_t k, hipStream_t s) {
+  hipLaunchKernelGGL(advance_one_kernel, dim3(1), dim3(1), 0, s, st, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const PopDesc* descs_dev, uint32_t ndesc,
+                         hipStream_t s) {
+  if (ndesc == 0) return hipSuccess;
+  hipLaunchKernelGGL(finish_kernel, dim3(ndesc), dim3(kBlock), 0, s, descs_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_one(const PopDesc& d, hipStream_t s) {
+  hipLaunchKernelGGL(finish_one_kernel, dim3(1), dim3(kBlock), 0, s, d);
   return hipGetLastError();
 }
 

@@ -45,7 +45,11 @@ void free_run(RunBuffers* b) {
 
 MultiLaunch::~MultiLaunch() {
   if (graph_) (void)hipGraphExecDestroy(graph_);
-  if (capture_) (void)hipStreamDestroy(capture_);
+  if (capture_) {
+    (void)hipStreamDestroy(capture_);
+    for (auto b : branch_) (void)hipStreamDestroy(b);
+    for (auto e : fork_) (void)hipEventDestroy(e);
+  }
   for (Group& g : groups_) {
     if (g.desc) (void)hipFree(g.desc);
     if (g.map) (void)hipFree(g.map);
@@ -74,6 +78,7 @@ ga_status MultiLaunch::set(const PopDesc* descs, uint32_t count,
       ds.push_back(d);
     }
     g.nblocks = (uint32_t)map.size();
+    g.ndesc = (uint32_t)ds.size();
     if (ds.empty()) continue;
     if (ds.size() > g.cap_desc) {
       if (g.desc) GA_TRY(hipFree(g.desc), "hipFree");
@@ -99,29 +104,61 @@ ga_status MultiLaunch::set(const PopDesc* descs, uint32_t count,
   return GA_OK;
 }
 
-ga_status MultiLaunch::enqueue_generation(hipStream_t s) {
+ga_status MultiLaunch::enqueue_generation(uint32_t node, hipStream_t s) {
   for (Group& g : groups_)
     if (g.nblocks)
-      GA_TRY(launch_children(g.desc, g.map, g.nblocks, g.m, s),
+      GA_TRY(launch_children(g.desc, g.map, g.nblocks, g.m, node, s),
              "children kernel");
   return GA_OK;
 }
 
+ga_status MultiLaunch::finish(hipStream_t s) {
+  for (Group& g : groups_)
+    if (g.ndesc) GA_TRY(launch_finish(g.desc, g.ndesc, s), "finish kernel");
+  return GA_OK;
+}
+
+// The chunk graph holds one independent chain per order group (a group's
+// generation G depends only on its own generation G - 1): the capture forks
+// one stream per group from the capture stream and joins them at the end,
+// so the groups' launches may run side by side.
 ga_status MultiLaunch::launch_chunk(uint32_t gens, hipStream_t s) {
   if (!graph_ || graph_gens_ != gens) {
     if (graph_) {
       GA_TRY(hipGraphExecDestroy(graph_), "hipGraphExecDestroy");
       graph_ = nullptr;
     }
-    if (!capture_)
+    if (!capture_) {
       GA_TRY(hipStreamCreateWithFlags(&capture_, hipStreamNonBlocking),
              "hipStreamCreate");
+      for (auto& b : branch_)
+        GA_TRY(hipStreamCreateWithFlags(&b, hipStreamNonBlocking),
+               "hipStreamCreate");
+      for (auto& e : fork_)
+        GA_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming),
+               "hipEventCreate");
+    }
     hipGraph_t g;
     GA_TRY(hipStreamBeginCapture(capture_, hipStreamCaptureModeThreadLocal),
            "hipStreamBeginCapture");
-    ga_status st = GA_OK;
-    for (uint32_t i = 0; i < gens && st == GA_OK; ++i)
-      st = enqueue_generation(capture_);
+    ga_status st = hip_status(hipEventRecord(fork_[9], capture_), "hipEventRecord");
+    for (int gi = 0; gi < 9 && st == GA_OK; ++gi) {
+      Group& gr = groups_[gi];
+      if (!gr.ndesc) continue;
+      hipStream_t b = branch_[gi];
+      st = hip_status(hipStreamWaitEvent(b, fork_[9], 0), "hipStreamWaitEvent");
+      for (uint32_t i = 0; i < gens && st == GA_OK; ++i)
+        st = hip_status(launch_children(gr.desc, gr.map, gr.nblocks, gr.m, i, b),
+                        "children kernel");
+      if (st == GA_OK)
+        st = hip_status(launch_advance(gr.desc, gr.ndesc, gens, b),
+                        "advance kernel");
+      if (st == GA_OK)
+        st = hip_status(hipEventRecord(fork_[gi], b), "hipEventRecord");
+      if (st == GA_OK)
+        st = hip_status(hipStreamWaitEvent(capture_, fork_[gi], 0),
+                        "hipStreamWaitEvent");
+    }
     hipError_t ce = hipStreamEndCapture(capture_, &g);
     if (st != GA_OK) return st;
     GA_TRY(ce, "hipStreamEndCapture");
@@ -137,12 +174,9 @@ ga_status MultiLaunch::launch_chunk(uint32_t gens, hipStream_t s) {
 // Starts a run in place: state reset, initial population, its fitness.
 static ga_status start_run(const ga_config* c, const RunBuffers& b,
                            RunState* st, hipStream_t s) {
-  const uint32_t stop_on_found = (c->flags & GA_STOP_ON_FOUND) ? 1u : 0u;
   GA_TRY(launch_reset_state(st, s), "state kernel");
   GA_TRY(launch_init(c, b.pop_a, s), "init kernel");
   GA_TRY(launch_fitness(c, b.pop_a, b.keys_a, nullptr, st, s), "fitness kernel");
-  GA_TRY(launch_gen0_finish(st, stop_on_found, c->max_generations, s),
-         "state kernel");
   return GA_OK;
 }
 
@@ -217,8 +251,8 @@ extern "C" ga_status ga_run_batch(const ga_config* cfgs, uint32_t count,
     if (rc != GA_OK) break;
     const uint32_t chunk = std::min<uint32_t>(32, std::max<uint32_t>(gmax, 1));
     uint32_t enq = 0;
-    bool all_stopped = false;
-    while (!all_stopped && enq < gmax) {
+    bool all_done = false;
+    while (!all_done && enq < gmax) {
       rc = ml.launch_chunk(chunk, s);
       if (rc != GA_OK) break;
       enq += chunk;
@@ -228,9 +262,13 @@ extern "C" ga_status ga_run_batch(const ga_config* cfgs, uint32_t count,
       if (rc != GA_OK) break;
       rc = hip_status(hipStreamSynchronize(s), "hipStreamSynchronize");
       if (rc != GA_OK) break;
-      all_stopped = true;
-      for (uint32_t i = 0; i < count; ++i) all_stopped &= host[i].stop != 0;
+      all_done = true;
+      for (uint32_t i = 0; i < count; ++i)
+        all_done &= run_done(host[i], cfgs[i].max_generations,
+                             (cfgs[i].flags & GA_STOP_ON_FOUND) != 0);
     }
+    if (rc != GA_OK) break;
+    rc = ml.finish(s);
     if (rc != GA_OK) break;
     rc = hip_status(hipMemcpyAsync(host, states, count * sizeof(RunState),
                                    hipMemcpyDeviceToHost, s),
@@ -238,15 +276,9 @@ extern "C" ga_status ga_run_batch(const ga_config* cfgs, uint32_t count,
     if (rc != GA_OK) break;
     rc = hip_status(hipStreamSynchronize(s), "hipStreamSynchronize");
     if (rc != GA_OK) break;
-    for (uint32_t i = 0; i < count && rc == GA_OK; ++i) {
-      if (!host[i].stop) {
-        set_error("batched run %u did not reach its stop condition", i);
-        rc = GA_EDEVICE;
-        break;
-      }
+    for (uint32_t i = 0; i < count && rc == GA_OK; ++i)
       rc = read_result(&cfgs[i], host[i], bufs[i].pop_a, bufs[i].pop_b,
                        &outs[i]);
-    }
   } while (0);
   cleanup();
   return rc;

@@ -23,7 +23,21 @@ struct SelArgs {
   RunState* st;
   uint64_t seed;
   uint32_t n, count, mw, paper;
+  uint32_t node, max_gen, stop_on_found;
 };
+
+// Generation G produced by this launch and whether it runs (see RunState);
+// the selection reads generation G - 1.
+__device__ __forceinline__ bool sel_generation(const SelArgs& a, uint32_t* G) {
+  *G = __hip_atomic_load(&a.st->gen_base, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT) + a.node + 1;
+  if (*G > a.max_gen) return false;
+  if (a.stop_on_found &&
+      __hip_atomic_load(&a.st->found_gen, __ATOMIC_RELAXED,
+                        __HIP_MEMORY_SCOPE_AGENT) < *G)
+    return false;
+  return true;
+}
 
 // Finds the bin holding the target-th element (1-based) of a 4096-bin
 // histogram; returns (bin, count before bin).  Clears the histogram.
@@ -52,8 +66,9 @@ __device__ void scan_find(uint32_t* hist, uint32_t target, uint32_t* bin_out,
 }
 
 __global__ __launch_bounds__(kBlock) void sel_hist_hi(SelArgs a) {
-  if (ld_acq(&a.st->stop)) return;
-  const uint32_t g = ld_acq(&a.st->gen);
+  uint32_t G;
+  if (!sel_generation(a, &G)) return;
+  const uint32_t g = G - 1;
   const uint32_t* keys = (g & 1u) ? a.keys_b : a.keys_a;
   __shared__ uint32_t h[4096];
   for (int i = threadIdx.x; i < 4096; i += kBlock) h[i] = 0;
@@ -77,8 +92,9 @@ __global__ __launch_bounds__(kBlock) void sel_hist_hi(SelArgs a) {
 }
 
 __global__ __launch_bounds__(kBlock) void sel_hist_lo(SelArgs a) {
-  if (ld_acq(&a.st->stop)) return;
-  const uint32_t g = ld_acq(&a.st->gen);
+  uint32_t G;
+  if (!sel_generation(a, &G)) return;
+  const uint32_t g = G - 1;
   const uint32_t* keys = (g & 1u) ? a.keys_b : a.keys_a;
   const uint32_t bucket = ld_acq(&a.ws->bucket);
   __shared__ uint32_t h[4096];
@@ -108,8 +124,9 @@ __global__ __launch_bounds__(kBlock) void sel_hist_lo(SelArgs a) {
 // Per tile of kSelTile keys: how many are < T and == T; the last block
 // turns the per-tile counts into exclusive offsets.
 __global__ __launch_bounds__(kBlock) void sel_count(SelArgs a) {
-  if (ld_acq(&a.st->stop)) return;
-  const uint32_t g = ld_acq(&a.st->gen);
+  uint32_t G;
+  if (!sel_generation(a, &G)) return;
+  const uint32_t g = G - 1;
   const uint32_t* keys = (g & 1u) ? a.keys_b : a.keys_a;
   const uint32_t T = ld_acq(&a.ws->T);
   const uint32_t base = blockIdx.x * kSelTile;
@@ -182,9 +199,9 @@ __device__ uint32_t perm_inverse(uint64_t seed, uint32_t G, uint32_t D,
 // Stable compaction: the selected individuals, in index order, are copied to
 // slots rank (elitism) or pi^-1(rank) (paper mode) of the next generation.
 __global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a) {
-  if (ld_acq(&a.st->stop)) return;
-  const uint32_t g = ld_acq(&a.st->gen);
-  const uint32_t G = g + 1;
+  uint32_t G;
+  if (!sel_generation(a, &G)) return;
+  const uint32_t g = G - 1;
   const bool odd = (g & 1u) != 0;
   const uint32_t* keys = odd ? a.keys_b : a.keys_a;
   const uint32_t* pop = odd ? a.pop_b : a.pop_a;
@@ -204,7 +221,6 @@ __global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a) {
   uint32_t dummy;
   uint32_t lb = block_exclusive_scan(cl, &dummy) + a.ws->blk_less[blockIdx.x];
   uint32_t eb = block_exclusive_scan(ce, &dummy) + a.ws->blk_eq[blockIdx.x];
-  unsigned long long best = ~0ull;
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
     const uint32_t i = i0 + e;
@@ -221,35 +237,32 @@ __global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a) {
         uint4* d4 = reinterpret_cast<uint4*>(pout + (size_t)slot * a.mw);
         for (uint32_t v = 0; v < a.mw / 4; ++v) d4[v] = s4[v];
         kout[slot] = kk[e];
-        const unsigned long long cand =
-            ((unsigned long long)kk[e] << 32) | slot;
-        best = cand < best ? cand : best;
       }
     }
     lb += less;
     eb += eq;
   }
-  best = block_min_u64(best);
-  if (threadIdx.x == 0 && best != ~0ull) atomicMin(&a.st->best[G & 1u], best);
 }
 
-hipError_t launch_select(const ga_config* c, uint32_t* pop_a, uint32_t* pop_b,
-                         uint32_t* keys_a, uint32_t* keys_b, uint32_t count,
-                         SelWork* ws, RunState* st, hipStream_t s) {
+hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
+                         uint32_t node, hipStream_t s) {
   SelArgs a;
-  a.pop_a = pop_a;
-  a.pop_b = pop_b;
-  a.keys_a = keys_a;
-  a.keys_b = keys_b;
+  a.pop_a = d.pop_a;
+  a.pop_b = d.pop_b;
+  a.keys_a = d.keys_a;
+  a.keys_b = d.keys_b;
   a.ws = ws;
-  a.st = st;
-  a.seed = c->seed;
-  a.n = c->n;
+  a.st = d.state;
+  a.seed = d.seed;
+  a.n = d.n;
   a.count = count;
-  a.mw = c->m * ((c->m + 31) / 32);
-  a.paper = c->selection == GA_SEL_PAPER;
-  const uint32_t gh = std::min<uint32_t>(cdiv(c->n, kBlock * 8), 1024);
-  const uint32_t gt = cdiv(c->n, kSelTile);
+  a.mw = d.m * ((d.m + 31) / 32);
+  a.paper = d.paper;
+  a.node = node;
+  a.max_gen = d.max_gen;
+  a.stop_on_found = d.stop_on_found;
+  const uint32_t gh = std::min<uint32_t>(cdiv(d.n, kBlock * 8), 1024);
+  const uint32_t gt = cdiv(d.n, kSelTile);
   hipLaunchKernelGGL(sel_hist_hi, dim3(gh), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(sel_hist_lo, dim3(gh), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(sel_count, dim3(gt), dim3(kBlock), 0, s, a);

@@ -156,12 +156,26 @@ static void worker_main(ga_server* S) {
     if (st != GA_OK) break;
     std::vector<Request*> still;
     for (Request* r : active) {
-      if (!host[r->slot].stop) {
+      if (!run_done(host[r->slot], r->cfg.max_generations,
+                    (r->cfg.flags & GA_STOP_ON_FOUND) != 0)) {
         still.push_back(r);
         continue;
       }
-      ga_status rr = read_result(&r->cfg, host[r->slot], r->buf.pop_a,
-                                 r->buf.pop_b, &r->result);
+      const PopDesc d = make_desc(&r->cfg, r->buf.pop_a, r->buf.pop_b,
+                                  r->buf.keys_a, r->buf.keys_b,
+                                  &states[r->slot], r->cfg.max_generations,
+                                  (r->cfg.flags & GA_STOP_ON_FOUND) ? 1u : 0u);
+      ga_status rr = hip_status(launch_finish_one(d, stream), "finish kernel");
+      if (rr == GA_OK)
+        rr = hip_status(hipMemcpyAsync(&host[r->slot], &states[r->slot],
+                                       sizeof(RunState), hipMemcpyDeviceToHost,
+                                       stream),
+                        "hipMemcpyAsync(state)");
+      if (rr == GA_OK)
+        rr = hip_status(hipStreamSynchronize(stream), "hipStreamSynchronize");
+      if (rr == GA_OK)
+        rr = read_result(&r->cfg, host[r->slot], r->buf.pop_a, r->buf.pop_b,
+                         &r->result);
       free_run(&r->buf);
       free_slots.push_back(r->slot);
       finish(S, r, rr, rr == GA_OK ? nullptr : ga_last_error());
