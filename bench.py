@@ -25,8 +25,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz of 32-bit integer vector ALU issue
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# MI355X 32-bit vector ALU issue: the fp32 vector peak of 157.3 TFLOP/s is
+# 256 CUs x 128 FMA lanes per clock x 2 flops x 2.4 GHz; integer xor,
+# popcount and 24-bit multiply-add issue at the same lane rate:
+# 256 x 128 x 2.4 GHz = 78.6 T ops/s
+ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 
 
 def ops_per_eval(m: int, kind: int) -> int:
@@ -131,8 +134,10 @@ def bench_default(args):
     dt = timed_runs(cfg, bufs, args.steps)
     dt_abs = timed_runs(cfg_abs, bufs, args.steps)
     evals = n * (G + 1)
-    # roofline of the fused children kernel: one more run with each launch
-    # bracketed by HIP events on the library's stream
+    # roofline of the fused children kernel: one more run with HIP events on
+    # the library's stream around its generation loop; with tournament
+    # selection and no elites each generation is one children launch, so the
+    # mean time per generation is that kernel's launch-to-launch time
     ga.ga_timing_enable(True)
     ga.ga_run(cfg, *bufs)
     mean_ms, launches = ga.ga_timing_read()
@@ -160,7 +165,7 @@ def bench_default(args):
         "roofline": {"bound": "alu", "kernel": "children_one_kernel<20>",
                      "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
-                     "mean_launch_ms": mean_ms, "launches": launches,
+                     "mean_generation_ms": mean_ms, "generations_timed": launches,
                      "ops_per_eval": ops_per_eval(m, ga.FIT_SQ)},
     }
     if not args.no_cpu_baseline:

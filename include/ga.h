@@ -202,12 +202,11 @@ ga_status ga_check_invariants(const ga_config* cfg, const uint32_t* pop,
                               uint32_t* bad_count, void* stream);
 
 /*
- * Kernel timing, for measurement.  While enabled, ga_step and ga_run
- * bracket each generation's children launch (the fused selection,
- * crossover, mutation and fitness kernel) with HIP events recorded on the
- * launch stream.  ga_timing_read waits for the recorded events and returns
- * the mean duration in milliseconds and the number of timed launches since
- * the last ga_timing_enable(1).  Not thread-safe; meant for benchmarks.
+ * Timing, for measurement.  While enabled, ga_run records HIP events on its
+ * stream around its generation loop (the chunks of children launches, one
+ * launch per generation).  ga_timing_read returns the mean time per
+ * generation in milliseconds and the number of generations timed since the
+ * last ga_timing_enable(1).  Not thread-safe; meant for benchmarks.
  */
 ga_status ga_timing_enable(int on);
 ga_status ga_timing_read(double* mean_ms, uint64_t* launches);

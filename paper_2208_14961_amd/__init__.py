@@ -220,8 +220,8 @@ def ga_timing_enable(on: bool) -> None:
 
 
 def ga_timing_read():
-    """(mean duration in ms, number) of the children launches timed since
-    ga_timing_enable(True)."""
+    """(mean time per generation in ms, generations) of the ga_run
+    generation loops timed since ga_timing_enable(True)."""
     ms = ctypes.c_double()
     n = ctypes.c_uint64()
     _check(lib().ga_timing_read(ctypes.byref(ms), ctypes.byref(n)))

@@ -44,15 +44,25 @@ def _device_asm(src: str) -> str:
 
 
 def check_no_calls(asm_path: str) -> None:
-    """Every kernel must be call-free.  A body the compiler outlines into a
-    function longer than a conditional branch can reach gets long branches
-    that reuse the return-address registers, and such a function never
-    returns; keeping kernels free of calls rules that out."""
+    """Every kernel must be call-free and use no scratch memory.  A body the
+    compiler outlines into a function longer than a conditional branch can
+    reach gets long branches that reuse the return-address registers, and
+    such a function never returns; keeping kernels free of calls rules that
+    out.  Scratch (a register array indexed at run time, or spills) turns the
+    register-resident individual into per-lane memory traffic."""
     with open(asm_path) as f:
         text = f.read()
     if "s_swappc_b64" in text:
         raise RuntimeError(f"{asm_path}: a kernel makes a function call (s_swappc_b64); "
                            "force-inline the callee or split the kernel")
+    name = None
+    for line in text.splitlines():
+        line = line.strip()
+        if line.startswith(".name:"):
+            name = line.split(":", 1)[1].strip()
+        elif line.startswith(".private_segment_fixed_size:"):
+            if int(line.split(":", 1)[1]) != 0:
+                raise RuntimeError(f"{asm_path}: kernel {name} uses scratch memory ({line})")
 
 
 def _compile(src: str) -> tuple[str, float]:

@@ -167,27 +167,20 @@ PopDesc make_desc(const ga_config* c, uint32_t* pa, uint32_t* pb,
   d.max_gen = max_gen;
   d.stop_on_found = stop_on_found;
   d.block_begin = 0;
-  d.nblocks = (d.nchild + kChildBlock - 1) / kChildBlock;
+  const uint32_t per_block = c->m <= 32 ? kQuadChildren : kChildBlock;
+  d.nblocks = (d.nchild + per_block - 1) / per_block;
   return d;
 }
 
-// Optional event timing of the children launches (ga_timing_*).
+// Optional timing of ga_run's generation loop (ga_timing_*): HIP events on
+// the loop's stream around the chunk launches; the mean is per generation.
 struct Timing {
   bool on = false;
-  std::vector<hipEvent_t> pool;     // reusable events
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
-  size_t used = 0;
+  hipEvent_t start = nullptr, stop = nullptr;
+  double total_ms = 0;
+  uint64_t gens = 0;
 };
 static Timing g_timing;
-
-static hipEvent_t timing_event() {
-  if (g_timing.used == g_timing.pool.size()) {
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    g_timing.pool.push_back(e);
-  }
-  return g_timing.pool[g_timing.used++];
-}
 
 static uint32_t select_count(const ga_config* c) {
   if (c->selection == GA_SEL_PAPER) return c->n / 2;
@@ -202,17 +195,7 @@ static ga_status enqueue_generation(const ga_config* c, const PopDesc& d,
   const uint32_t cnt = select_count(c);
   if (cnt > 0)
     GA_TRY(launch_select(d, cnt, w->sel, node, s), "selection kernels");
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (g_timing.on) {
-    e0 = timing_event();
-    e1 = timing_event();
-    if (e0 && e1) GA_TRY(hipEventRecord(e0, s), "hipEventRecord");
-  }
   GA_TRY(launch_children_one(d, node, s), "children kernel");
-  if (e0 && e1) {
-    GA_TRY(hipEventRecord(e1, s), "hipEventRecord");
-    g_timing.marks.emplace_back(e0, e1);
-  }
   return GA_OK;
 }
 
@@ -341,13 +324,7 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
   // while chunk k+1 runs; launches past the end of the run return at once.
   const uint32_t chunk = std::min<uint32_t>(64, std::max<uint32_t>(1, cfg->max_generations));
   const uint32_t nchunks = (cfg->max_generations + chunk - 1) / chunk;
-  if (g_timing.on) {
-    // measurement mode: direct launches, each children kernel timed
-    for (uint32_t i = 0; i < cfg->max_generations; ++i) {
-      st = enqueue_generation(cfg, d, w, i, s);
-      if (st != GA_OK) return st;
-    }
-  } else if (nchunks > 0) {
+  if (nchunks > 0) {
     std::vector<char> key(sizeof(PopDesc) + sizeof(ga_config));
     memcpy(key.data(), &d, sizeof(PopDesc));
     memcpy(key.data() + sizeof(PopDesc), cfg, sizeof(ga_config));
@@ -375,6 +352,7 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     // the capture stream starts after the work already enqueued on s
     GA_TRY(hipEventRecord(w->ev[2], s), "hipEventRecord");
     GA_TRY(hipStreamWaitEvent(w->capture, w->ev[2], 0), "hipStreamWaitEvent");
+    if (g_timing.on) GA_TRY(hipEventRecord(g_timing.start, w->capture), "hipEventRecord");
     auto launch_chunk = [&](uint32_t k) -> ga_status {
       GA_TRY(hipGraphLaunch(w->graph, w->capture), "hipGraphLaunch");
       GA_TRY(hipMemcpyAsync(&w->host_state[k & 1], w->state, sizeof(RunState),
@@ -394,6 +372,21 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
       if (run_done(w->host_state[k & 1], cfg->max_generations, stop_on_found))
         break;
     }
+    if (g_timing.on) {
+      // the chunks launched after the stop condition return at once; the
+      // mean is over the generations the run made
+      GA_TRY(hipEventRecord(g_timing.stop, w->capture), "hipEventRecord");
+      GA_TRY(hipEventSynchronize(g_timing.stop), "hipEventSynchronize");
+      float ms = 0;
+      GA_TRY(hipEventElapsedTime(&ms, g_timing.start, g_timing.stop),
+             "hipEventElapsedTime");
+      const RunState& hs = w->host_state[0].gen_base >= w->host_state[1].gen_base
+                               ? w->host_state[0] : w->host_state[1];
+      uint32_t made = std::min(cfg->max_generations, hs.gen_base);
+      if (stop_on_found && hs.found_gen < made) made = hs.found_gen;
+      g_timing.total_ms += ms;
+      g_timing.gens += made;
+    }
     // s continues after everything the capture stream did
     GA_TRY(hipEventRecord(w->ev[2], w->capture), "hipEventRecord");
     GA_TRY(hipStreamWaitEvent(s, w->ev[2], 0), "hipStreamWaitEvent");
@@ -408,10 +401,14 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
 }
 
 ga_status ga_timing_enable(int on) {
+  if (on && !g_timing.start) {
+    GA_TRY(hipEventCreate(&g_timing.start), "hipEventCreate");
+    GA_TRY(hipEventCreate(&g_timing.stop), "hipEventCreate");
+  }
   g_timing.on = on != 0;
   if (g_timing.on) {
-    g_timing.marks.clear();
-    g_timing.used = 0;
+    g_timing.total_ms = 0;
+    g_timing.gens = 0;
   }
   return GA_OK;
 }
@@ -421,15 +418,8 @@ ga_status ga_timing_read(double* mean_ms, uint64_t* launches) {
     set_error("ga_timing_read needs two outputs");
     return GA_EINVAL;
   }
-  double total = 0;
-  for (auto& m : g_timing.marks) {
-    GA_TRY(hipEventSynchronize(m.second), "hipEventSynchronize");
-    float ms = 0;
-    GA_TRY(hipEventElapsedTime(&ms, m.first, m.second), "hipEventElapsedTime");
-    total += ms;
-  }
-  *launches = g_timing.marks.size();
-  *mean_ms = g_timing.marks.empty() ? 0.0 : total / g_timing.marks.size();
+  *launches = g_timing.gens;
+  *mean_ms = g_timing.gens ? g_timing.total_ms / (double)g_timing.gens : 0.0;
   return GA_OK;
 }
 

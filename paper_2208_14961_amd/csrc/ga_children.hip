@@ -1,8 +1,10 @@
 // ga_children.hip -- one generation's children: parent selection,
 // column-exchange crossover (Sec. 3.4), pair-flip mutation (Sec. 3.5) and
-// the child's fitness (Sec. 3.2), one lane per child, fused in one kernel.
-// Generation G = state->gen + 1 is produced from generation G - 1; the run
-// state's last block closes the generation (best key, stop flag).
+// the child's fitness (Sec. 3.2), fused in one kernel: four lanes per child
+// for orders up to 32, one lane per child above.
+// Launch `node` of a chunk produces generation G = gen_base + node + 1 from
+// generation G - 1; a wave that makes a child of fitness 0 lowers the run's
+// found_gen to G.
 #include <hip/hip_runtime.h>
 
 #include "ga_common.h"
@@ -54,110 +56,253 @@ __device__ __forceinline__ Parents pick_parents(const PopDesc& d, uint32_t G,
   return r;
 }
 
-// The four 32-bit words of a lane's Philox block, swapped with lane ^ 1.
-__device__ __forceinline__ U4 shfl_xor1(const U4& v) {
-  return U4{(uint32_t)__shfl_xor((int)v.x, 1, 64),
-            (uint32_t)__shfl_xor((int)v.y, 1, 64),
-            (uint32_t)__shfl_xor((int)v.z, 1, 64),
-            (uint32_t)__shfl_xor((int)v.w, 1, 64)};
+// ---------------------------------------------------------------------------
+// Orders up to 32: four lanes per child, eight per child pair.
+//
+// Lane 8g + t of a block works on pair g of the block: child c = t / 4, part
+// l = t for child 0 and 7 - t for child 1, so the lane holding part l of one
+// child and the lane holding part l of its sibling are mirror images within
+// the eight lanes (one DPP half-row mirror).  Part v of an individual is its
+// 16-byte word group v (columns 4v .. 4v+3); lane part l holds groups l,
+// l+4, ...  Each lane computes one Philox block of the pair (quad position
+// 0: selection, 1: crossover, 2 and 3: mutation of child 0 and 1) and the
+// quad shares them by DPP broadcasts.  A tournament reads the contestants'
+// keys first and then only the winner's columns.  For the fitness the child
+// is staged in LDS, and lane l takes the column pairs (i, i + d mod C),
+// C = M - 1 odd, d = 1 .. (C-1)/2, for i in its quarter of 0 .. C-1: every
+// unordered pair of columns 1 .. M-1 exactly once.  The quad then sums its
+// four partial sums.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
 }
 
-// Orders up to 32: the child lives in registers from crossover to store.
-// The two children of a pair sit in lanes q and q ^ 1 of one wave: for
-// binary tournaments each computes one of the pair's two Philox blocks
-// (selection, crossover) and one tournament, and they swap the results.
-// All draws come before the dependent loads, so their latency overlaps the
-// arithmetic.  Lanes past the last child compute a copy of the last pair
-// and store nothing.
+// Quad position S's value in all four lanes of each quad.
+template <int S>
+__device__ __forceinline__ U4 quad_bcast(const U4& v) {
+  constexpr int C = S | (S << 2) | (S << 4) | (S << 6);
+  return U4{dpp_mov<C>(v.x), dpp_mov<C>(v.y), dpp_mov<C>(v.z), dpp_mov<C>(v.w)};
+}
+
+// Lane 7 - i's value within each group of eight lanes (row_half_mirror).
+__device__ __forceinline__ uint32_t mirror8(uint32_t v) { return dpp_mov<0x141>(v); }
+
+// Sum over the four lanes of each quad, in every lane.
+__device__ __forceinline__ uint32_t quad_sum(uint32_t v) {
+  v += dpp_mov<0xB1>(v);  // lane ^ 1
+  v += dpp_mov<0x4E>(v);  // lane ^ 2
+  return v;
+}
+
+template <int M>
+struct Quad {
+  static constexpr int P4 = M / 4;             // 16-byte groups per individual
+  static constexpr int NP = (P4 + 3) / 4;      // groups per lane
+  static constexpr int F = 4 * NP;             // words per lane
+  static constexpr int C = M - 1;              // columns 1 .. M-1
+  static constexpr int D = (C - 1) / 2;        // pair distances
+  static constexpr int K = (C + 3) / 4;        // first columns per lane
+  static __device__ __forceinline__ bool has(int s, uint32_t l) {
+    return s * 4 + 4 <= P4 || l + 4u * s < (uint32_t)P4;
+  }
+};
+
+// Winner of tournament c of pair p (t contestants, draws c*t .. c*t+t-1 of
+// the pair's selection stream; block 0 is given): smallest key, then
+// smallest index.
+__device__ __forceinline__ uint32_t tournament(const PopDesc& d, uint32_t G,
+                                               uint32_t p, uint32_t c,
+                                               const U4& sel,
+                                               const uint32_t* kin) {
+  if (d.t == 2) {
+    const uint32_t x0 = bounded(c ? sel.z : sel.x, d.n);
+    const uint32_t x1 = bounded(c ? sel.w : sel.y, d.n);
+    const uint32_t k0 = kin[x0], k1 = kin[x1];
+    return (k1 < k0 || (k1 == k0 && x1 < x0)) ? x1 : x0;
+  }
+  DrawSeq ds(d.seed, kStreamSelect, G, p, sel);
+  uint32_t bx = bounded(ds.at(c * d.t), d.n);
+  uint32_t bk = kin[bx];
+  for (uint32_t k = 1; k < d.t; ++k) {
+    const uint32_t x = bounded(ds.at(c * d.t + k), d.n);
+    const uint32_t kx = kin[x];
+    if (kx < bk || (kx == bk && x < bx)) {
+      bx = x;
+      bk = kx;
+    }
+  }
+  return bx;
+}
+
+// Pair-flip mutation (Sec. 3.5, third method) of a child held as parts: the
+// lane holding the chosen column flips it; the draws are those of the
+// one-lane form (columns at draws 0 .. nc-1, row pairs after them).
+template <int M>
+__device__ __forceinline__ void mutate_parts(uint32_t (&f)[Quad<M>::F],
+                                             uint32_t l, DrawSeq& ds,
+                                             uint32_t nc, uint32_t nr) {
+  constexpr int F = Quad<M>::F;
+  for (uint32_t jc = 0; jc < nc; ++jc) {
+    const uint32_t col = 1u + bounded(ds.at(jc), M - 1);
+    const uint32_t v = col >> 2;
+    const uint32_t k = (v >> 2) * 4 + (col & 3u);  // word in this lane
+    uint32_t x = 0;
+    [&]<int... J>(std::integer_sequence<int, J...>) __attribute__((always_inline)) {
+      ((x |= pick_if_eq<J>(k, f[J])), ...);
+    }(std::make_integer_sequence<int, F>{});
+    uint32_t mask = 0;
+    for (uint32_t ir = 0; ir < nr; ++ir) {
+      const uint32_t r1 = bounded(ds.at(nc + 2 * ir), M);
+      const uint32_t r2 = bounded(ds.at(nc + 2 * ir + 1), M);
+      const uint32_t y = x ^ mask;
+      if (((y >> r1) ^ (y >> r2)) & 1u) mask ^= (1u << r1) | (1u << r2);
+    }
+    if ((v & 3u) != l) mask = 0;  // another lane holds the column
+    [&]<int... J>(std::integer_sequence<int, J...>) __attribute__((always_inline)) {
+      ((f[J] ^= pick_if_eq<J>(k, mask)), ...);
+    }(std::make_integer_sequence<int, F>{});
+  }
+}
+
+// This lane's share of the column-pair sums of the child staged at `me`.
+template <int M, uint32_t NEED>
+__device__ __forceinline__ Sums quad_pair_sums(const uint32_t* me, uint32_t l) {
+  using Q = Quad<M>;
+  constexpr int C = Q::C, D = Q::D, K = Q::K, H = M / 2;
+  const uint32_t r = l * K;
+  uint32_t z[K + D];
+#pragma unroll
+  for (int k = 0; k < K + D; ++k) {
+    uint32_t i = r + k;
+    i = i >= (uint32_t)C ? i - C : i;
+    z[k] = me[1 + i];
+  }
+  Sums s{0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (k + 3 * K < C) {  // column r + k exists in every lane
+#pragma unroll
+      for (int dd = 1; dd <= D; ++dd) pair_step<NEED>(z[k] ^ z[k + dd], 0u, 1, H, s);
+    } else {
+      Sums g{0, 0, 0};
+#pragma unroll
+      for (int dd = 1; dd <= D; ++dd) pair_step<NEED>(z[k] ^ z[k + dd], 0u, 1, H, g);
+      const bool in = r + k < (uint32_t)C;
+      s.sq += in ? g.sq : 0u;
+      s.ab += in ? g.ab : 0u;
+      s.nz += in ? g.nz : 0u;
+    }
+  }
+  return s;
+}
+
+template <int M>
+__device__ __forceinline__ uint32_t quad_fitness(const uint32_t* me, uint32_t l,
+                                                 uint32_t kind) {
+  Sums s;
+  switch (needs_of_kind(kind)) {  // uniform over the launch
+    case kNeedSQ:
+      s = quad_pair_sums<M, kNeedSQ>(me, l);
+      s.sq = quad_sum(s.sq);
+      break;
+    case kNeedABS:
+      s = quad_pair_sums<M, kNeedABS>(me, l);
+      s.ab = quad_sum(s.ab);
+      break;
+    case kNeedNNZ:
+      s = quad_pair_sums<M, kNeedNNZ>(me, l);
+      s.nz = quad_sum(s.nz);
+      break;
+    default:
+      s = quad_pair_sums<M, kNeedSQ | kNeedNNZ>(me, l);
+      s.sq = quad_sum(s.sq);
+      s.nz = quad_sum(s.nz);
+      break;
+  }
+  return key_of(kind, s);
+}
+
+// The child of this lane's quad in generation G; `lds` holds the block's
+// 16 children of M words.  Lanes of pairs past the last compute a copy of
+// the last pair and store nothing.
 template <int M>
 __device__ __forceinline__ unsigned long long child(const PopDesc& d,
-                                                   uint32_t G, uint32_t q) {
+                                                   uint32_t G, uint32_t* lds) {
+  using Q = Quad<M>;
   constexpr uint32_t MW = M;
   const bool odd_in = ((G - 1) & 1u) != 0;
   const uint32_t* pin = odd_in ? d.pop_b : d.pop_a;
   const uint32_t* kin = odd_in ? d.keys_b : d.keys_a;
   uint32_t* pout = odd_in ? d.pop_a : d.pop_b;
   uint32_t* kout = odd_in ? d.keys_a : d.keys_b;
-  const bool valid = q < d.nchild;
+  const uint32_t lane = threadIdx.x, t = lane & 7u, u = lane & 3u;
+  const uint32_t c = t >> 2, l = c ? 7u - t : t;
+  const uint32_t pw = (blockIdx.x - d.block_begin) * (kChildBlock / 8) + (lane >> 3);
   const uint32_t npairs = (d.nchild + 1) >> 1;
-  const uint32_t p = min(q >> 1, npairs - 1), c = q & 1u;
-  const bool binary = !d.paper && d.t == 2;  // uniform over the launch
-  U4 xo, sel;
-  if (binary) {
-    const U4 mine = draw_block(d.seed, c ? kStreamXover : kStreamSelect, G, p, 0);
-    const U4 other = shfl_xor1(mine);
-    sel = c ? other : mine;
-    xo = c ? mine : other;
+  const uint32_t p = min(pw, npairs - 1);
+  const uint32_t q = 2 * p + c;
+  const bool valid = 2 * pw + c < d.nchild;
+
+  const uint32_t stream = u == 0 ? kStreamSelect : (u == 1 ? kStreamXover : kStreamMutate);
+  const U4 blk = draw_block(d.seed, stream, G, u < 2 ? p : 2 * p + (u - 2), 0);
+  const U4 sel = quad_bcast<0>(blk);
+  const U4 xo = quad_bcast<1>(blk);
+  const U4 mb0 = quad_bcast<2>(blk), mb1 = quad_bcast<3>(blk);
+
+  // this child's first parent (its columns before the cut) and slot
+  const uint32_t* first;
+  uint32_t dst;
+  if (d.paper) {
+    const uint32_t N = d.n / 4;
+    first = pout + (size_t)(c ? p + N : p) * MW;
+    dst = (c ? 3u * N : 2u * N) + p;
   } else {
-    xo = draw_block(d.seed, kStreamXover, G, p, 0);
-    sel = xo;
+    first = pin + (size_t)tournament(d, G, p, c, sel, kin) * MW;
+    dst = d.elite + q;
   }
-  const bool mut = (uint64_t)(c ? xo.w : xo.z) < d.mut_thr;
+  const uint4* f4 = reinterpret_cast<const uint4*>(first);
+  uint32_t f[Q::F];
+#pragma unroll
+  for (int s = 0; s < Q::NP; ++s) {
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (Q::has(s, l)) v = f4[l + 4 * s];
+    f[4 * s] = v.x;
+    f[4 * s + 1] = v.y;
+    f[4 * s + 2] = v.z;
+    f[4 * s + 3] = v.w;
+  }
+  // column-exchange crossover (Sec. 3.4): columns >= cut from the sibling's
+  // first parent
   const uint32_t cut =
       ((uint64_t)xo.x < d.xo_thr) ? 1u + bounded(xo.y, M - 1) : (uint32_t)M;
-  // first mutation block, drawn before the loads
-  U4 mb0 = U4{0, 0, 0, 0};
-  if (mut) mb0 = draw_block(d.seed, kStreamMutate, G, q, 0);
-  // parents
-  const uint32_t* A;
-  const uint32_t* B;
-  uint32_t dst;
-  if (binary) {
-    const uint32_t x0 = bounded(c ? sel.z : sel.x, d.n);
-    const uint32_t x1 = bounded(c ? sel.w : sel.y, d.n);
-    const uint32_t k0 = kin[x0], k1 = kin[x1];
-    const uint32_t w = (k1 < k0 || (k1 == k0 && x1 < x0)) ? x1 : x0;
-    const uint32_t wo = (uint32_t)__shfl_xor((int)w, 1, 64);
-    A = pin + (size_t)(c ? wo : w) * MW;
-    B = pin + (size_t)(c ? w : wo) * MW;
-    dst = d.elite + q;
-  } else {
-    const Parents par = pick_parents(d, G, 2 * p + c, MW, pin, kin, pout);
-    A = par.A;
-    B = par.B;
-    dst = par.dst;
-  }
-  const uint32_t* first = c ? B : A;
-  const uint32_t* second = c ? A : B;
-  // mutation (Sec. 3.5): up to four columns by flip masks computed from the
-  // parents' words, applied while crossing over; more columns use the
-  // general in-register path
-  uint32_t mcol[4] = {0, 0, 0, 0}, mmask[4] = {0, 0, 0, 0};
-  const bool fast = d.nc <= 4;
-  if (mut && fast) {
-    DrawSeq ds(d.seed, kStreamMutate, G, q, mb0);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if ((uint32_t)k < d.nc) {
-        const uint32_t col = 1u + bounded(ds.at(k), M - 1);
-        uint32_t v = ((col < cut) ? first : second)[col];
+  for (int s = 0; s < Q::NP; ++s) {
 #pragma unroll
-        for (int kp = 0; kp < k; ++kp)
-          if (mcol[kp] == col) v ^= mmask[kp];
-        uint32_t mask = 0;
-        for (uint32_t ir = 0; ir < d.nr; ++ir) {
-          const uint32_t r1 = bounded(ds.at(d.nc + 2 * ir), M);
-          const uint32_t r2 = bounded(ds.at(d.nc + 2 * ir + 1), M);
-          const uint32_t x = v ^ mask;
-          if (((x >> r1) ^ (x >> r2)) & 1u) mask ^= (1u << r1) | (1u << r2);
-        }
-        mcol[k] = col;
-        mmask[k] = mask;
-      }
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t o = mirror8(f[4 * s + e]);
+      f[4 * s + e] = (4u * (l + 4u * s) + e < cut) ? f[4 * s + e] : o;
     }
   }
-  Cols<M> cols;
-  load_crossed<M>(first, second, cut, cols);
-  if (mut) {
-    if (fast)
-      apply_masks<M>(cols, d.nc, mcol, mmask);
-    else
-      mutate<M>(cols, d.seed, G, q, d.nc, d.nr);
+  if ((uint64_t)(c ? xo.w : xo.z) < d.mut_thr) {
+    DrawSeq ds(d.seed, kStreamMutate, G, q, c ? mb1 : mb0);
+    mutate_parts<M>(f, l, ds, d.nc, d.nr);
   }
-  const uint32_t key = fitness<M>(cols, d.kind, false, nullptr);
+  uint32_t* me = lds + ((lane >> 3) * 2 + c) * M;
+#pragma unroll
+  for (int s = 0; s < Q::NP; ++s)
+    if (Q::has(s, l))
+      reinterpret_cast<uint4*>(me)[l + 4 * s] =
+          make_uint4(f[4 * s], f[4 * s + 1], f[4 * s + 2], f[4 * s + 3]);
+  __syncthreads();
+  const uint32_t key = quad_fitness<M>(me, l, d.kind);
   if (!valid) return ~0ull;
-  store_cols<M>(pout + (size_t)dst * MW, cols);
-  kout[dst] = key;
+  uint4* o4 = reinterpret_cast<uint4*>(pout + (size_t)dst * MW);
+#pragma unroll
+  for (int s = 0; s < Q::NP; ++s)
+    if (Q::has(s, l))
+      o4[l + 4 * s] = make_uint4(f[4 * s], f[4 * s + 1], f[4 * s + 2], f[4 * s + 3]);
+  if (l == 0) kout[dst] = key;
   return ((unsigned long long)key << 32) | dst;
 }
 
@@ -211,17 +356,14 @@ __device__ __forceinline__ unsigned long long child_w2(const PopDesc& d,
   return ((unsigned long long)key << 32) | par.dst;
 }
 
-// Generation G of launch `node`, and whether it runs (see RunState).
+// Generation G of launch `node`, and whether it runs (see RunState).  The
+// state was last written by an earlier kernel, so plain loads see it.
 __device__ __forceinline__ bool generation_of(const PopDesc& d, uint32_t node,
                                               uint32_t* G) {
-  const RunState* st = d.state;
-  *G = __hip_atomic_load(&st->gen_base, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT) + node + 1;
+  const uint2 v = *reinterpret_cast<const uint2*>(&d.state->gen_base);
+  *G = v.x + node + 1;  // v.x = gen_base, v.y = found_gen
   if (*G > d.max_gen) return false;
-  if (d.stop_on_found &&
-      __hip_atomic_load(&st->found_gen, __ATOMIC_RELAXED,
-                        __HIP_MEMORY_SCOPE_AGENT) < *G)
-    return false;
+  if (d.stop_on_found && v.y < *G) return false;
   return true;
 }
 
@@ -231,24 +373,25 @@ __device__ __forceinline__ void children_block(const PopDesc& d, uint32_t node,
                                                F&& body) {
   uint32_t G;
   if (!generation_of(d, node, &G)) return;  // uniform over the launch
-  const uint32_t q = (blockIdx.x - d.block_begin) * kChildBlock + threadIdx.x;
-  note_zero(d.state, body(G, q), G);
+  const unsigned long long b = body(G);
+  if (d.stop_on_found) note_zero(d.state, b, G);
 }
 
 // One population, order M <= 32, descriptor by value.
 template <int M>
 __global__ __launch_bounds__(kChildBlock) void children_one_kernel(PopDesc d,
                                                                    uint32_t node) {
-  children_block(d, node, [&](uint32_t G, uint32_t q) __attribute__((always_inline)) {
-    return child<M>(d, G, q);
+  __shared__ uint32_t lds[kQuadChildren * M];
+  children_block(d, node, [&](uint32_t G) __attribute__((always_inline)) {
+    return child<M>(d, G, lds);
   });
 }
 
 // One population, order 36..64.
 __global__ __launch_bounds__(kChildBlock) void children_one_w2_kernel(
     PopDesc d, uint32_t node) {
-  children_block(d, node, [&](uint32_t G, uint32_t q) __attribute__((always_inline)) {
-    return child_w2(d, G, q);
+  children_block(d, node, [&](uint32_t G) __attribute__((always_inline)) {
+    return child_w2(d, G, (blockIdx.x - d.block_begin) * kChildBlock + threadIdx.x);
   });
 }
 
@@ -262,9 +405,10 @@ template <int M>
 __global__ __launch_bounds__(kChildBlock) void children_multi_kernel(
     const PopDesc* __restrict__ descs, const uint32_t* __restrict__ block_pop,
     uint32_t node) {
+  __shared__ uint32_t lds[kQuadChildren * M];
   const PopDesc d = descs[block_pop[blockIdx.x]];
-  children_block(d, node, [&](uint32_t G, uint32_t q) __attribute__((always_inline)) {
-    return child<M>(d, G, q);
+  children_block(d, node, [&](uint32_t G) __attribute__((always_inline)) {
+    return child<M>(d, G, lds);
   });
 }
 
@@ -273,8 +417,8 @@ __global__ __launch_bounds__(kChildBlock) void children_multi_w2_kernel(
     const PopDesc* __restrict__ descs, const uint32_t* __restrict__ block_pop,
     uint32_t node) {
   const PopDesc d = descs[block_pop[blockIdx.x]];
-  children_block(d, node, [&](uint32_t G, uint32_t q) __attribute__((always_inline)) {
-    return child_w2(d, G, q);
+  children_block(d, node, [&](uint32_t G) __attribute__((always_inline)) {
+    return child_w2(d, G, (blockIdx.x - d.block_begin) * kChildBlock + threadIdx.x);
   });
 }
 

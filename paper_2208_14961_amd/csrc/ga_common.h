@@ -47,8 +47,8 @@ __device__ __forceinline__ unsigned long long wave_min_u64(
 __device__ __forceinline__ void note_zero(RunState* st,
                                           unsigned long long lane_best,
                                           uint32_t G) {
-  const unsigned long long b = wave_min_u64(lane_best);
-  if ((threadIdx.x & 63) == 0 && (b >> 32) == 0) atomicMin(&st->found_gen, G);
+  const bool zero = (lane_best >> 32) == 0;  // invalid lanes carry ~0
+  if (__ballot(zero) && (threadIdx.x & 63) == 0) atomicMin(&st->found_gen, G);
 }
 
 // Exclusive prefix sum over the block (blockDim.x == kBlock); also returns

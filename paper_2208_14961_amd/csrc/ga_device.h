@@ -360,26 +360,6 @@ __device__ __forceinline__ uint32_t pick_if_eq(uint32_t a, uint32_t x) {
   return r;
 }
 
-// Column-exchange crossover while loading, plus up to four mutation masks:
-// word j = (j < cut ? first : second)[j] ^ sum over k of (col[k] == j ?
-// mask[k] : 0).  Unused mask slots have col = 0, which no column j >= 1
-// matches (column 0 is never mutated).
-template <int M>
-__device__ __forceinline__ void apply_masks(Cols<M>& c, uint32_t nmask,
-                                            const uint32_t (&col)[4],
-                                            const uint32_t (&mask)[4]) {
-  static_assert(M <= 32, "register path holds one word per column");
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if ((uint32_t)k < nmask) {
-      // compile-time column indices: each j is its own register
-      [&]<int... J>(std::integer_sequence<int, J...>) __attribute__((always_inline)) {
-        ((c.w[J + 1][0] ^= pick_if_eq<J + 1>(col[k], mask[k])), ...);
-      }(std::make_integer_sequence<int, M - 1>{});
-    }
-  }
-}
-
 // Pair-flip mutation (Sec. 3.5, third method) of child ordinal q in
 // generation G, register-resident (M <= 32), any number of columns: nc
 // columns, nr row pairs shared by the columns; a pair is negated only when

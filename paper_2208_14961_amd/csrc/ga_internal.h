@@ -13,6 +13,7 @@ constexpr uint32_t kMaxElite = 1u << 16;    // elite count limit
 constexpr uint32_t kKeyBits = 24;           // selection ranks keys < 2^24
 constexpr int kBlock = 256;                 // threads per block, bulk kernels
 constexpr int kChildBlock = 64;             // one wave per block: children
+constexpr int kQuadChildren = 16;           // children per block, orders <= 32
 constexpr int kSelTile = 2048;              // elements per block, selection
 constexpr int kMaxSelBlocks = 8192;         // kMaxN / kSelTile
 

@@ -29,13 +29,10 @@ struct SelArgs {
 // Generation G produced by this launch and whether it runs (see RunState);
 // the selection reads generation G - 1.
 __device__ __forceinline__ bool sel_generation(const SelArgs& a, uint32_t* G) {
-  *G = __hip_atomic_load(&a.st->gen_base, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT) + a.node + 1;
+  const uint2 v = *reinterpret_cast<const uint2*>(&a.st->gen_base);
+  *G = v.x + a.node + 1;  // v.x = gen_base, v.y = found_gen
   if (*G > a.max_gen) return false;
-  if (a.stop_on_found &&
-      __hip_atomic_load(&a.st->found_gen, __ATOMIC_RELAXED,
-                        __HIP_MEMORY_SCOPE_AGENT) < *G)
-    return false;
+  if (a.stop_on_found && v.y < *G) return false;
   return true;
 }
 
