@@ -162,7 +162,7 @@ def bench_default(args):
         "generations_per_s": args.steps * G / dt,
         "abs_keyed": {"value": args.steps * evals / dt_abs, "unit": "evals/s",
                       "generations_per_s": args.steps * G / dt_abs},
-        "roofline": {"bound": "alu", "kernel": "children_one_kernel<20>",
+        "roofline": {"bound": "alu", "kernel": "children_one_kernel<20, SQ>",
                      "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
                      "mean_generation_ms": mean_ms, "generations_timed": launches,

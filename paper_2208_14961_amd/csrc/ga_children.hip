@@ -139,29 +139,42 @@ __device__ __forceinline__ uint32_t tournament(const PopDesc& d, uint32_t G,
 // lane holding the chosen column flips it; the draws are those of the
 // one-lane form (columns at draws 0 .. nc-1, row pairs after them).
 template <int M>
+__device__ __forceinline__ void flip_parts(uint32_t (&f)[Quad<M>::F], uint32_t l,
+                                           uint32_t col, uint32_t r1,
+                                           uint32_t r2, uint32_t& mask,
+                                           bool apply) {
+  constexpr int F = Quad<M>::F;
+  const uint32_t v = col >> 2;
+  const uint32_t k = (v >> 2) * 4 + (col & 3u);  // word in this lane
+  uint32_t x = 0;
+  [&]<int... J>(std::integer_sequence<int, J...>) __attribute__((always_inline)) {
+    ((x |= pick_if_eq<J>(k, f[J])), ...);
+  }(std::make_integer_sequence<int, F>{});
+  const uint32_t y = x ^ mask;
+  if (((y >> r1) ^ (y >> r2)) & 1u) mask ^= (1u << r1) | (1u << r2);
+  if (!apply) return;
+  const uint32_t mk = (v & 3u) == l ? mask : 0u;  // another lane holds the column
+  [&]<int... J>(std::integer_sequence<int, J...>) __attribute__((always_inline)) {
+    ((f[J] ^= pick_if_eq<J>(k, mk)), ...);
+  }(std::make_integer_sequence<int, F>{});
+}
+
+template <int M>
 __device__ __forceinline__ void mutate_parts(uint32_t (&f)[Quad<M>::F],
                                              uint32_t l, DrawSeq& ds,
                                              uint32_t nc, uint32_t nr) {
-  constexpr int F = Quad<M>::F;
+  if (nc == 1 && nr == 1) {  // draws 0, 1, 2: all in the given block 0
+    uint32_t mask = 0;
+    flip_parts<M>(f, l, 1u + bounded(ds.cur.x, M - 1), bounded(ds.cur.y, M),
+                  bounded(ds.cur.z, M), mask, true);
+    return;
+  }
   for (uint32_t jc = 0; jc < nc; ++jc) {
     const uint32_t col = 1u + bounded(ds.at(jc), M - 1);
-    const uint32_t v = col >> 2;
-    const uint32_t k = (v >> 2) * 4 + (col & 3u);  // word in this lane
-    uint32_t x = 0;
-    [&]<int... J>(std::integer_sequence<int, J...>) __attribute__((always_inline)) {
-      ((x |= pick_if_eq<J>(k, f[J])), ...);
-    }(std::make_integer_sequence<int, F>{});
     uint32_t mask = 0;
-    for (uint32_t ir = 0; ir < nr; ++ir) {
-      const uint32_t r1 = bounded(ds.at(nc + 2 * ir), M);
-      const uint32_t r2 = bounded(ds.at(nc + 2 * ir + 1), M);
-      const uint32_t y = x ^ mask;
-      if (((y >> r1) ^ (y >> r2)) & 1u) mask ^= (1u << r1) | (1u << r2);
-    }
-    if ((v & 3u) != l) mask = 0;  // another lane holds the column
-    [&]<int... J>(std::integer_sequence<int, J...>) __attribute__((always_inline)) {
-      ((f[J] ^= pick_if_eq<J>(k, mask)), ...);
-    }(std::make_integer_sequence<int, F>{});
+    for (uint32_t ir = 0; ir < nr; ++ir)
+      flip_parts<M>(f, l, col, bounded(ds.at(nc + 2 * ir), M),
+                    bounded(ds.at(nc + 2 * ir + 1), M), mask, ir + 1 == nr);
   }
 }
 
@@ -197,36 +210,33 @@ __device__ __forceinline__ Sums quad_pair_sums(const uint32_t* me, uint32_t l) {
   return s;
 }
 
-template <int M>
+template <int M, uint32_t NEED>
+__device__ __forceinline__ uint32_t quad_fitness_need(const uint32_t* me,
+                                                      uint32_t l, uint32_t kind) {
+  Sums s = quad_pair_sums<M, NEED>(me, l);
+  if (NEED & kNeedSQ) s.sq = quad_sum(s.sq);
+  if (NEED & kNeedABS) s.ab = quad_sum(s.ab);
+  if (NEED & kNeedNNZ) s.nz = quad_sum(s.nz);
+  return key_of(kind, s);
+}
+
+// Key of the staged child.  NEED = 0: the sums are chosen at run time.
+template <int M, uint32_t NEED>
 __device__ __forceinline__ uint32_t quad_fitness(const uint32_t* me, uint32_t l,
                                                  uint32_t kind) {
-  Sums s;
+  if (NEED) return quad_fitness_need<M, NEED>(me, l, kind);
   switch (needs_of_kind(kind)) {  // uniform over the launch
-    case kNeedSQ:
-      s = quad_pair_sums<M, kNeedSQ>(me, l);
-      s.sq = quad_sum(s.sq);
-      break;
-    case kNeedABS:
-      s = quad_pair_sums<M, kNeedABS>(me, l);
-      s.ab = quad_sum(s.ab);
-      break;
-    case kNeedNNZ:
-      s = quad_pair_sums<M, kNeedNNZ>(me, l);
-      s.nz = quad_sum(s.nz);
-      break;
-    default:
-      s = quad_pair_sums<M, kNeedSQ | kNeedNNZ>(me, l);
-      s.sq = quad_sum(s.sq);
-      s.nz = quad_sum(s.nz);
-      break;
+    case kNeedSQ: return quad_fitness_need<M, kNeedSQ>(me, l, kind);
+    case kNeedABS: return quad_fitness_need<M, kNeedABS>(me, l, kind);
+    case kNeedNNZ: return quad_fitness_need<M, kNeedNNZ>(me, l, kind);
+    default: return quad_fitness_need<M, kNeedSQ | kNeedNNZ>(me, l, kind);
   }
-  return key_of(kind, s);
 }
 
 // The child of this lane's quad in generation G; `lds` holds the block's
 // 16 children of M words.  Lanes of pairs past the last compute a copy of
 // the last pair and store nothing.
-template <int M>
+template <int M, uint32_t NEED>
 __device__ __forceinline__ unsigned long long child(const PopDesc& d,
                                                    uint32_t G, uint32_t* lds) {
   using Q = Quad<M>;
@@ -295,7 +305,7 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d,
       reinterpret_cast<uint4*>(me)[l + 4 * s] =
           make_uint4(f[4 * s], f[4 * s + 1], f[4 * s + 2], f[4 * s + 3]);
   __syncthreads();
-  const uint32_t key = quad_fitness<M>(me, l, d.kind);
+  const uint32_t key = quad_fitness<M, NEED>(me, l, d.kind);
   if (!valid) return ~0ull;
   uint4* o4 = reinterpret_cast<uint4*>(pout + (size_t)dst * MW);
 #pragma unroll
@@ -377,13 +387,14 @@ __device__ __forceinline__ void children_block(const PopDesc& d, uint32_t node,
   if (d.stop_on_found) note_zero(d.state, b, G);
 }
 
-// One population, order M <= 32, descriptor by value.
-template <int M>
+// One population, order M <= 32, the sums its fitness kind needs fixed at
+// compile time, descriptor by value.
+template <int M, uint32_t NEED>
 __global__ __launch_bounds__(kChildBlock) void children_one_kernel(PopDesc d,
                                                                    uint32_t node) {
   __shared__ uint32_t lds[kQuadChildren * M];
   children_block(d, node, [&](uint32_t G) __attribute__((always_inline)) {
-    return child<M>(d, G, lds);
+    return child<M, NEED>(d, G, lds);
   });
 }
 
@@ -408,7 +419,7 @@ __global__ __launch_bounds__(kChildBlock) void children_multi_kernel(
   __shared__ uint32_t lds[kQuadChildren * M];
   const PopDesc d = descs[block_pop[blockIdx.x]];
   children_block(d, node, [&](uint32_t G) __attribute__((always_inline)) {
-    return child<M>(d, G, lds);
+    return child<M, 0>(d, G, lds);
   });
 }
 
@@ -443,19 +454,39 @@ hipError_t launch_children(const PopDesc* descs_dev, const uint32_t* block_pop,
   return hipGetLastError();
 }
 
+template <int M>
+static void launch_one_order(const PopDesc& d, uint32_t node, hipStream_t s) {
+  const dim3 grid(d.nblocks), block(kChildBlock);
+  switch (needs_of_kind(d.kind)) {
+    case kNeedSQ:
+      hipLaunchKernelGGL((children_one_kernel<M, kNeedSQ>), grid, block, 0, s, d, node);
+      break;
+    case kNeedABS:
+      hipLaunchKernelGGL((children_one_kernel<M, kNeedABS>), grid, block, 0, s, d, node);
+      break;
+    case kNeedNNZ:
+      hipLaunchKernelGGL((children_one_kernel<M, kNeedNNZ>), grid, block, 0, s, d, node);
+      break;
+    default:
+      hipLaunchKernelGGL((children_one_kernel<M, kNeedSQ | kNeedNNZ>), grid, block, 0,
+                         s, d, node);
+  }
+}
+
 hipError_t launch_children_one(const PopDesc& d, uint32_t node, hipStream_t s) {
   if (d.nblocks == 0) return hipSuccess;
-  const dim3 grid(d.nblocks), block(kChildBlock);
   switch (d.m) {
-#define GA_CH_CASE(MM)                                                      \
-  case MM:                                                                  \
-    hipLaunchKernelGGL(children_one_kernel<MM>, grid, block, 0, s, d, node);\
-    break;
-    GA_CH_CASE(4) GA_CH_CASE(8) GA_CH_CASE(12) GA_CH_CASE(16)
-    GA_CH_CASE(20) GA_CH_CASE(24) GA_CH_CASE(28) GA_CH_CASE(32)
-#undef GA_CH_CASE
+    case 4: launch_one_order<4>(d, node, s); break;
+    case 8: launch_one_order<8>(d, node, s); break;
+    case 12: launch_one_order<12>(d, node, s); break;
+    case 16: launch_one_order<16>(d, node, s); break;
+    case 20: launch_one_order<20>(d, node, s); break;
+    case 24: launch_one_order<24>(d, node, s); break;
+    case 28: launch_one_order<28>(d, node, s); break;
+    case 32: launch_one_order<32>(d, node, s); break;
     default:
-      hipLaunchKernelGGL(children_one_w2_kernel, grid, block, 0, s, d, node);
+      hipLaunchKernelGGL(children_one_w2_kernel, dim3(d.nblocks), dim3(kChildBlock), 0,
+                         s, d, node);
   }
   return hipGetLastError();
 }

@@ -50,8 +50,20 @@ __host__ __device__ inline uint32_t needs_of_kind(uint32_t kind) {
 
 struct U4 {
   uint32_t x, y, z, w;
+  // Word i (0..3) by selects: written as plain conditionals the compiler
+  // may copy the four words to scratch and index them there.
   __device__ uint32_t operator[](uint32_t i) const {
-    return i == 0 ? x : (i == 1 ? y : (i == 2 ? z : w));
+    uint32_t r;
+    asm("v_cmp_eq_u32 vcc, 1, %1\n\t"
+        "v_cndmask_b32 %0, %2, %3, vcc\n\t"
+        "v_cmp_eq_u32 vcc, 2, %1\n\t"
+        "v_cndmask_b32 %0, %0, %4, vcc\n\t"
+        "v_cmp_eq_u32 vcc, 3, %1\n\t"
+        "v_cndmask_b32 %0, %0, %5, vcc"
+        : "=&v"(r)
+        : "v"(i), "v"(x), "v"(y), "v"(z), "v"(w)
+        : "vcc");
+    return r;
   }
 };
 
