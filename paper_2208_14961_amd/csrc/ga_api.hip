@@ -167,7 +167,7 @@ PopDesc make_desc(const ga_config* c, uint32_t* pa, uint32_t* pb,
   d.max_gen = max_gen;
   d.stop_on_found = stop_on_found;
   d.block_begin = 0;
-  const uint32_t per_block = c->m <= 32 ? kQuadChildren : kChildBlock;
+  const uint32_t per_block = c->m <= 32 ? kQuadChildren : kOctChildren;
   d.nblocks = (d.nchild + per_block - 1) / per_block;
   return d;
 }

@@ -14,6 +14,8 @@ constexpr uint32_t kKeyBits = 24;           // selection ranks keys < 2^24
 constexpr int kBlock = 256;                 // threads per block, bulk kernels
 constexpr int kChildBlock = 64;             // one wave per block: children
 constexpr int kQuadChildren = 16;           // children per block, orders <= 32
+constexpr int kOctChildren = 8;             // children per block, orders >= 36
+constexpr int kOrders = 16;                 // orders 4, 8, .., 64
 constexpr int kSelTile = 2048;              // elements per block, selection
 constexpr int kMaxSelBlocks = 8192;         // kMaxN / kSelTile
 
@@ -151,18 +153,18 @@ class MultiLaunch {
 
  private:
   struct Group {
-    uint32_t m = 0;                  // order (orders > 32 share group m = 64)
+    uint32_t m = 0;                  // order
     PopDesc* desc = nullptr;
     uint32_t* map = nullptr;
     size_t cap_desc = 0, cap_map = 0;
     uint32_t ndesc = 0, nblocks = 0;
   };
-  Group groups_[9];                  // orders 4..32 step 4, then 36..64
+  Group groups_[kOrders];            // one per order 4, 8, .., 64
   hipGraphExec_t graph_ = nullptr;
   uint32_t graph_gens_ = 0;
   hipStream_t capture_ = nullptr;
-  hipStream_t branch_[9] = {};       // capture branches, one per group
-  hipEvent_t fork_[10] = {};         // join events per group, fork event
+  hipStream_t branch_[kOrders] = {};  // capture branches, one per group
+  hipEvent_t fork_[kOrders + 1] = {};  // join events per group, fork event
 };
 
 }  // namespace ga

@@ -56,7 +56,7 @@ MultiLaunch::~MultiLaunch() {
   }
 }
 
-static int group_of(uint32_t m) { return m <= 32 ? (int)(m / 4) - 1 : 8; }
+static int group_of(uint32_t m) { return (int)(m / 4) - 1; }
 
 ga_status MultiLaunch::set(const PopDesc* descs, uint32_t count,
                            hipStream_t s) {
@@ -64,9 +64,9 @@ ga_status MultiLaunch::set(const PopDesc* descs, uint32_t count,
     GA_TRY(hipGraphExecDestroy(graph_), "hipGraphExecDestroy");
     graph_ = nullptr;
   }
-  for (int gi = 0; gi < 9; ++gi) {
+  for (int gi = 0; gi < kOrders; ++gi) {
     Group& g = groups_[gi];
-    g.m = gi < 8 ? 4u * (gi + 1) : 64u;
+    g.m = 4u * (gi + 1);
     std::vector<PopDesc> ds;
     std::vector<uint32_t> map;
     for (uint32_t i = 0; i < count; ++i) {
@@ -141,12 +141,12 @@ ga_status MultiLaunch::launch_chunk(uint32_t gens, hipStream_t s) {
     hipGraph_t g;
     GA_TRY(hipStreamBeginCapture(capture_, hipStreamCaptureModeThreadLocal),
            "hipStreamBeginCapture");
-    ga_status st = hip_status(hipEventRecord(fork_[9], capture_), "hipEventRecord");
-    for (int gi = 0; gi < 9 && st == GA_OK; ++gi) {
+    ga_status st = hip_status(hipEventRecord(fork_[kOrders], capture_), "hipEventRecord");
+    for (int gi = 0; gi < kOrders && st == GA_OK; ++gi) {
       Group& gr = groups_[gi];
       if (!gr.ndesc) continue;
       hipStream_t b = branch_[gi];
-      st = hip_status(hipStreamWaitEvent(b, fork_[9], 0), "hipStreamWaitEvent");
+      st = hip_status(hipStreamWaitEvent(b, fork_[kOrders], 0), "hipStreamWaitEvent");
       for (uint32_t i = 0; i < gens && st == GA_OK; ++i)
         st = hip_status(launch_children(gr.desc, gr.map, gr.nblocks, gr.m, i, b),
                         "children kernel");
