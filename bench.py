@@ -13,10 +13,12 @@ m = 8, n = 1,024 plain GA over 32 seeds.
 --workload batched: 24 runs in one batched launch per generation against
 the same 24 runs one after another.
 --workload served: a Poisson stream of search requests through the server.
+--workload pmc: a short run for hardware-counter passes (no timing).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -121,6 +123,52 @@ def time_to_solve(runs=32):
             "mean_generations": (sum(gens) / len(gens)) if gens else None}
 
 
+def workload_pmc(args):
+    """Short run for hardware-counter passes: the default workload's kernel
+    for one 64-generation chunk, then a plain 256 MiB device copy whose
+    counter reading calibrates the byte counters."""
+    import torch
+    import paper_2208_14961_amd as ga
+    cfg = ga.Config(m=20, n=40000, seed=1, fitness=ga.FIT_SQ, max_generations=64, flags=0)
+    bufs = buffers(cfg)
+    r = ga.ga_run(cfg, *bufs)
+    x = torch.ones(64 * 1024 * 1024, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    return {"workload": "counter pass: m=20 n=40000 SQ, 64 generations; 256 MiB copy",
+            "best_key": r["best_key"], "copy_bytes": 2 * x.numel() * 4}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "children_m20_n40000_traffic.md")
+TRAFFIC_SOURCES = ["paper_2208_14961_amd/csrc/ga_children.hip",
+                   "paper_2208_14961_amd/csrc/ga_device.h"]
+
+
+def sources_digest() -> str:
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per children launch from the committed counter summary, or
+    None when the kernel sources have changed since it was measured."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(block)
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("sources_sha256") != sources_digest():
+        return None
+    return rec
+
+
 def bench_default(args):
     import torch
     import paper_2208_14961_amd as ga
@@ -143,6 +191,8 @@ def bench_default(args):
     mean_ms, launches = ga.ga_timing_read()
     ga.ga_timing_enable(False)
     achieved = n * ops_per_eval(m, ga.FIT_SQ) / (mean_ms * 1e-3) / 1e12
+    tr = measured_traffic()
+    traffic = None if tr is None else tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
     out = {
         "metric": "Gram+fitness evals/s and generations/s at m=20,pop=40k; p50/p99 time-to-solve",
         "value": args.steps * evals / dt,
@@ -164,7 +214,7 @@ def bench_default(args):
                       "generations_per_s": args.steps * G / dt_abs},
         "roofline": {"bound": "alu", "kernel": "children_one_kernel<20, SQ>",
                      "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                     "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
                      "mean_generation_ms": mean_ms, "generations_timed": launches,
                      "ops_per_eval": ops_per_eval(m, ga.FIT_SQ)},
     }
@@ -248,7 +298,12 @@ def bench_served(args):
         if a > now:
             time.sleep(a - now)
         ids.append(srv.submit(c))
-    results = [srv.wait(i) for i in ids]
+    results = []
+    for k, i in enumerate(ids):
+        results.append(srv.wait(i))
+        if (k + 1) % 100 == 0:
+            print(f"served: {k + 1}/{count} requests retired after "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
     lat = [srv.latency(i) for i in ids]
     srv.close()
@@ -274,20 +329,23 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="default", choices=["default", "batched", "served"])
+    ap.add_argument("--workload", default="default",
+                    choices=["default", "batched", "served", "pmc"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(independent runs would shard by run; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(independent runs would be sharded by run, one process per GPU).",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    fn = {"default": bench_default, "batched": bench_batched, "served": bench_served}
+    fn = {"default": bench_default, "batched": bench_batched, "served": bench_served,
+          "pmc": workload_pmc}
     out = fn[args.workload](args)
     print(json.dumps(out), flush=True)
 

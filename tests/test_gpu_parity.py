@@ -246,6 +246,23 @@ def test_run_batch_equals_single_runs():
         assert np.array_equal(got["matrix"], opop[want["index"]])
 
 
+def test_run_batch_every_order():
+    """One run of every order 4..64 in one batched launch sequence: each
+    order has its own batched children kernel."""
+    torch_cuda()
+    kinds = [ga.FIT_SQ, ga.FIT_ABS, ga.FIT_NNZ, ga.FIT_SQ_PLUS_NNZ, ga.FIT_F1, ga.FIT_F2]
+    cfgs = [ga.Config(m=m, n=200 + 37 * i, seed=7_000_000 + m, fitness=kinds[i % 6],
+                      max_generations=4 + i % 5, flags=0, nc=1 + i % 2, nr=1 + i % 3)
+            for i, m in enumerate(ORDERS)]
+    announce("batch every order", len(cfgs))
+    batch = ga.ga_run_batch(cfgs)
+    for cfg, got in zip(cfgs, batch):
+        want, opop, _ = gao.run(to_oracle(cfg))
+        for k in ("found", "generation", "index", "best_key"):
+            assert got[k] == want[k], (cfg, got, want)
+        assert np.array_equal(got["matrix"], opop[want["index"]])
+
+
 def test_server_results_equal_alone_and_mixed():
     torch_cuda()
     cfgs = _mixed_configs()
