@@ -83,8 +83,7 @@ hipError_t launch_fitness(const ga_config* c, const uint32_t* pop,
 // pi^-1(rank)), G from the state and the launch's node
 hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
                          uint32_t node, hipStream_t s);
-// children of every population in descs (device array); all of order m if
-// m <= 32, else all of orders 36..64
+// children of every population in descs (device array), all of order m
 hipError_t launch_children(const PopDesc* descs_dev, const uint32_t* block_pop,
                            uint32_t total_blocks, uint32_t m, uint32_t node,
                            hipStream_t s);
@@ -135,8 +134,8 @@ ga_status start_runs(const ga_config* cfgs, const RunBuffers* bufs,
                      RunState* states, uint32_t count, hipStream_t s);
 
 // Launch tables of a set of runs: one descriptor per run, and the map from
-// a block of the children launch to its run, per group (one group per order
-// up to 32, one group for orders 36..64).
+// a block of the children launch to its run, per group (one group per
+// order).
 class MultiLaunch {
  public:
   ~MultiLaunch();
