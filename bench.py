@@ -27,11 +27,30 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X 32-bit vector ALU issue: the fp32 vector peak of 157.3 TFLOP/s is
-# 256 CUs x 128 FMA lanes per clock x 2 flops x 2.4 GHz; integer xor,
-# popcount and 24-bit multiply-add issue at the same lane rate:
-# 256 x 128 x 2.4 GHz = 78.6 T ops/s
-ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+# MI355X 32-bit vector ALU issue, 256 CUs at 2.4 GHz.  Simple ops (xor,
+# add, compare, add-with-carry) issue at 128 lanes per clock per CU, the
+# lane rate of the 157.3 TFLOP/s fp32 vector peak: 78.6 T ops/s.  Popcount
+# (v_bcnt_u32_b32), the 24-bit multiply-add (v_mad_i32_i24) and v_sad_u32
+# issue at half that rate, 64 lanes per clock per CU: 39.3 T ops/s.
+SIMPLE_OP_TOPS = 256 * 128 * 2.4e9 / 1e12
+HALF_RATE_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def pair_mix(kind: int, w: int):
+    """(simple ops, half-rate ops) per column pair of the packed fitness:
+    w xors; w popcounts; the accumulation (SQ: multiply-add, ABS: sad, both
+    half rate; NNZ: compare + add-with-carry, simple)."""
+    import paper_2208_14961_amd as ga
+    acc = {ga.FIT_SQ: (0, 1), ga.FIT_ABS: (0, 1), ga.FIT_F1: (0, 1), ga.FIT_NNZ: (2, 0),
+           ga.FIT_F2: (2, 0), ga.FIT_SQ_PLUS_NNZ: (2, 1)}[kind]
+    return w + acc[0], w + acc[1]
+
+
+def alu_peak_tops(m: int, kind: int) -> float:
+    """Peak op rate of the pair loop's instruction mix: its ops divided by
+    the time the simple and half-rate ops take at their issue rates."""
+    simple, half = pair_mix(kind, (m + 31) // 32)
+    return (simple + half) / (simple / SIMPLE_OP_TOPS + half / HALF_RATE_TOPS)
 
 
 def ops_per_eval(m: int, kind: int) -> int:
@@ -39,12 +58,8 @@ def ops_per_eval(m: int, kind: int) -> int:
     per column pair (i < j, columns 1..m-1) one xor and one popcount per
     word plus the key's accumulation (SQ: one multiply-add of the centred
     count; ABS: one absolute-difference add; NNZ: compare + add)."""
-    import paper_2208_14961_amd as ga
-    w = (m + 31) // 32
     pairs = (m - 1) * (m - 2) // 2
-    acc = {ga.FIT_SQ: 1, ga.FIT_ABS: 1, ga.FIT_F1: 1, ga.FIT_NNZ: 2, ga.FIT_F2: 2,
-           ga.FIT_SQ_PLUS_NNZ: 3}[kind]
-    return pairs * (2 * w + acc)
+    return pairs * sum(pair_mix(kind, (m + 31) // 32))
 
 
 def percentile(xs, q):
@@ -169,6 +184,57 @@ def measured_traffic():
     return rec
 
 
+def gram_fitness_metric(reps=1000, repeats=5):
+    """The Gram + fitness kernel alone: the seed-1 m=20, n=40,000 initial
+    population evaluated `reps` times inside one launch (ga_fitness_repeat),
+    HIP events on the launch's stream, median of `repeats` launches."""
+    import torch
+    import paper_2208_14961_amd as ga
+    cfg = ga.Config(m=20, n=40000, seed=1, fitness=ga.FIT_SQ)
+    pop, _, keys, _ = buffers(cfg)
+    ga.ga_init_population(cfg, pop)
+    ga.ga_fitness_repeat(cfg, pop, keys, reps)  # warm
+    s = torch.cuda.current_stream()
+    times = []
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        ga.ga_fitness_repeat(cfg, pop, keys, reps)
+        e1.record(s)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = percentile(times, 50)
+    evals = cfg.n * reps / (ms * 1e-3)
+    tops = evals * ops_per_eval(cfg.m, cfg.fitness) / 1e12
+    peak = alu_peak_tops(cfg.m, cfg.fitness)
+    return {"kernel": "fitness_repeat_kernel<20, SQ>", "bound": "alu",
+            "workload": f"m=20, n=40000, seed-1 initial population, SQ key, {reps} evaluations "
+                        "of the whole population in one launch",
+            "median_ms": ms, "evals_per_s": evals, "achieved": tops, "peak": peak,
+            "unit": "TOP/s", "frac": tops / peak,
+            "frac_of_simple_op_peak": tops / SIMPLE_OP_TOPS}
+
+
+def elite_run_metric():
+    """Plain GA with elitism at m=32, n=200,000 (seed 2, SQ+NNZ key, the top
+    1% kept, 1000 generations, stop-on-found off): one whole run."""
+    import torch
+    import paper_2208_14961_amd as ga
+    cfg = ga.Config(m=32, n=200000, seed=2, fitness=ga.FIT_SQ_PLUS_NNZ, elite=2000,
+                    max_generations=1000, flags=0)
+    bufs = buffers(cfg)
+    ga.ga_run(ga.Config(**{**cfg.__dict__, "max_generations": 10}), *bufs)  # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = ga.ga_run(cfg, *bufs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    return {"workload": "plain GA m=32 n=200000 seed 2, SQ+NNZ, elite 2000, 1000 generations",
+            "seconds": dt, "generations_per_s": cfg.max_generations / dt,
+            "evals_per_s": (cfg.n - cfg.elite) * cfg.max_generations / dt,
+            "best_key": r["best_key"]}
+
+
 def bench_default(args):
     import torch
     import paper_2208_14961_amd as ga
@@ -191,6 +257,7 @@ def bench_default(args):
     mean_ms, launches = ga.ga_timing_read()
     ga.ga_timing_enable(False)
     achieved = n * ops_per_eval(m, ga.FIT_SQ) / (mean_ms * 1e-3) / 1e12
+    peak = alu_peak_tops(m, ga.FIT_SQ)
     tr = measured_traffic()
     traffic = None if tr is None else tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
     out = {
@@ -213,14 +280,17 @@ def bench_default(args):
         "abs_keyed": {"value": args.steps * evals / dt_abs, "unit": "evals/s",
                       "generations_per_s": args.steps * G / dt_abs},
         "roofline": {"bound": "alu", "kernel": "children_one_kernel<20, SQ>",
-                     "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
+                     "achieved": achieved, "peak": peak, "unit": "TOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "frac_of_simple_op_peak": achieved / SIMPLE_OP_TOPS,
                      "mean_generation_ms": mean_ms, "generations_timed": launches,
                      "ops_per_eval": ops_per_eval(m, ga.FIT_SQ)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, n, 1, ga.FIT_SQ, budget_s=args.cpu_seconds)
     out["time_to_solve"] = time_to_solve()
+    out["gram_fitness_kernel"] = gram_fitness_metric()
+    out["elite_run"] = elite_run_metric()
     return out
 
 

@@ -139,6 +139,17 @@ ga_status ga_fitness(const ga_config* cfg, const uint32_t* pop,
                      uint32_t* keys, uint32_t* comps, void* stream);
 
 /*
+ * The same Gram + fitness (Sec. 3.2), evaluated `reps` times over the whole
+ * population inside one launch: a throughput form of ga_fitness for
+ * measuring the Gram + fitness core without per-launch overhead.  Async.
+ * pop: [n][m][W] words, read.  keys: [n], written with cfg->fitness's key
+ * (every evaluation writes the same value; the result equals ga_fitness's).
+ * reps >= 1 and n * reps < 2^40, else GA_EINVAL.
+ */
+ga_status ga_fitness_repeat(const ga_config* cfg, const uint32_t* pop,
+                            uint32_t* keys, uint32_t reps, void* stream);
+
+/*
  * One generation, gen_in -> gen_in + 1 (Sec. 3, the loop body).  Async.
  * pop_in/keys_in (read) hold generation gen_in with its keys; pop_out and
  * keys_out (written, must not overlap the inputs) receive generation

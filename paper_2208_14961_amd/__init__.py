@@ -111,6 +111,7 @@ def lib() -> ctypes.CDLL:
             "ga_population_words": (ctypes.c_size_t, [P(_Config)]),
             "ga_init_population": (i32, [P(_Config), vp, vp]),
             "ga_fitness": (i32, [P(_Config), vp, vp, vp, vp]),
+            "ga_fitness_repeat": (i32, [P(_Config), vp, vp, u32, vp]),
             "ga_step": (i32, [P(_Config), vp, vp, vp, vp, u32, vp]),
             "ga_run": (i32, [P(_Config), vp, vp, vp, vp, P(_Result), vp]),
             "ga_run_batch": (i32, [P(_Config), u32, P(_Result), vp]),
@@ -182,6 +183,11 @@ def ga_fitness(cfg: Config, pop, keys, comps=None, stream=None) -> None:
     cp = _dev(comps, (cfg.n, 3), "comps") if comps is not None else None
     _check(lib().ga_fitness(ctypes.byref(cfg.c()), _dev(pop, pop_shape(cfg), "pop"),
                             _dev(keys, (cfg.n,), "keys"), cp, _stream(stream)))
+
+
+def ga_fitness_repeat(cfg: Config, pop, keys, reps: int, stream=None) -> None:
+    _check(lib().ga_fitness_repeat(ctypes.byref(cfg.c()), _dev(pop, pop_shape(cfg), "pop"),
+                                   _dev(keys, (cfg.n,), "keys"), reps, _stream(stream)))
 
 
 def ga_step(cfg: Config, pop_in, keys_in, pop_out, keys_out, gen_in: int,

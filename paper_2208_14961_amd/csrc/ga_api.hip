@@ -269,6 +269,28 @@ ga_status ga_fitness(const ga_config* cfg, const uint32_t* pop,
   return GA_OK;
 }
 
+ga_status ga_fitness_repeat(const ga_config* cfg, const uint32_t* pop,
+                            uint32_t* keys, uint32_t reps, void* stream) {
+  ga_status st = validate(cfg);
+  if (st != GA_OK) return st;
+  if (!pop || !keys) {
+    set_error("pop or keys is NULL");
+    return GA_EINVAL;
+  }
+  if (reps == 0 || (uint64_t)cfg->n * reps >= (1ull << 40)) {
+    set_error("reps=%u: need 1 <= reps and n * reps < 2^40", reps);
+    return GA_EINVAL;
+  }
+  int dev = 0, cus = 0;
+  GA_TRY(hipGetDevice(&dev), "hipGetDevice");
+  GA_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev),
+         "hipDeviceGetAttribute");
+  GA_TRY(launch_fitness_repeat(cfg, pop, keys, reps, (uint32_t)cus,
+                               (hipStream_t)stream),
+         "fitness kernel");
+  return GA_OK;
+}
+
 ga_status ga_step(const ga_config* cfg, const uint32_t* pop_in,
                   const uint32_t* keys_in, uint32_t* pop_out,
                   uint32_t* keys_out, uint32_t gen_in, void* stream) {

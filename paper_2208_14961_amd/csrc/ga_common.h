@@ -8,10 +8,6 @@
 
 namespace ga {
 
-__device__ __forceinline__ uint32_t ld_acq(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Block-wide minimum of a 64-bit value; the result is valid in thread 0.
 __device__ __forceinline__ unsigned long long block_min_u64(
     unsigned long long v) {
@@ -75,18 +71,6 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v,
   __syncthreads();
   *total = tot;
   return base + incl - v;
-}
-
-__device__ __forceinline__ bool last_block(uint32_t* counter) {
-  __shared__ bool s_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    if (s_last) __threadfence();
-  }
-  __syncthreads();
-  return s_last;
 }
 
 static inline uint32_t cdiv(uint64_t a, uint64_t b) {

@@ -68,7 +68,6 @@ struct SelWork {
   uint32_t blk_less[kMaxSelBlocks];
   uint32_t blk_eq[kMaxSelBlocks];
   uint32_t bucket, below, T, r;   // results of the radix select
-  uint32_t cnt[4];                // last-block counters
 };
 
 // ---- launchers (ga_kernels.hip, ga_children.hip, ga_select.hip) ---------
@@ -78,6 +77,11 @@ hipError_t launch_init(const ga_config* c, uint32_t* pop, hipStream_t s);
 hipError_t launch_fitness(const ga_config* c, const uint32_t* pop,
                           uint32_t* keys, uint32_t* comps, RunState* st,
                           hipStream_t s);
+// keys of all n, the population evaluated reps times in one launch over a
+// grid sized for `cus` compute units
+hipError_t launch_fitness_repeat(const ga_config* c, const uint32_t* pop,
+                                 uint32_t* keys, uint32_t reps, uint32_t cus,
+                                 hipStream_t s);
 // selection of the `count` smallest (key, index) of generation G - 1 into
 // generation G (elitism: slot = rank in index order; paper mode: slot =
 // pi^-1(rank)), G from the state and the launch's node

@@ -94,6 +94,39 @@ __global__ __launch_bounds__(kChildBlock) void fitness_kernel_w2(
   if (st) note_zero(st, best, 0);
 }
 
+// ga_fitness_repeat: evaluation i of the launch is individual i mod n, for
+// i < n * reps, strided over a grid sized to fill every CU.
+template <int M, uint32_t NEED>
+__global__ __launch_bounds__(kBlock) void fitness_repeat_kernel(
+    const uint32_t* __restrict__ pop, uint32_t n, uint64_t total, uint32_t kind,
+    uint32_t* __restrict__ keys) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint32_t k = (uint32_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) % n);
+  const uint32_t step = (uint32_t)(stride % n);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += stride) {
+    Cols<M> c;
+    load_cols<M>(pop + (size_t)k * M, c);
+    keys[k] = key_of(kind, pair_sums<M, NEED>(c));
+    k += step;
+    k = k >= n ? k - n : k;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void fitness_repeat_w2_kernel(
+    const uint32_t* __restrict__ pop, uint32_t n, uint32_t m, uint64_t total,
+    uint32_t kind, uint32_t* __restrict__ keys) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint32_t k = (uint32_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) % n);
+  const uint32_t step = (uint32_t)(stride % n);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += stride) {
+    keys[k] = fitness_w2(pop + (size_t)k * 2 * m, m, kind, false, nullptr);
+    k += step;
+    k = k >= n ? k - n : k;
+  }
+}
+
 __global__ void reset_state_kernel(RunState* st) {
   st->best = ~0ull;
   st->gen_base = 0;
@@ -225,6 +258,38 @@ hipError_t launch_fitness(const ga_config* c, const uint32_t* pop,
     GA_FIT_CASE(4) GA_FIT_CASE(8) GA_FIT_CASE(12) GA_FIT_CASE(16)
     GA_FIT_CASE(20) GA_FIT_CASE(24) GA_FIT_CASE(28) GA_FIT_CASE(32)
 #undef GA_FIT_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fitness_repeat(const ga_config* c, const uint32_t* pop,
+                                 uint32_t* keys, uint32_t reps, uint32_t cus,
+                                 hipStream_t s) {
+  const uint64_t total = (uint64_t)c->n * reps;
+  // eight workgroups of four waves per CU, fewer if the work is smaller
+  const uint64_t grid = std::min<uint64_t>((uint64_t)cus * 8, cdiv(total, kBlock));
+  if (c->m > 32) {
+    hipLaunchKernelGGL(fitness_repeat_w2_kernel, dim3((uint32_t)grid), dim3(kBlock), 0, s,
+                       pop, c->n, c->m, total, c->fitness, keys);
+    return hipGetLastError();
+  }
+  const uint32_t need = needs_of_kind(c->fitness);
+  switch (c->m) {
+#define GA_REP_NEED(MM, NN)                                                     \
+  hipLaunchKernelGGL((fitness_repeat_kernel<MM, NN>), dim3((uint32_t)grid),     \
+                     dim3(kBlock), 0, s, pop, c->n, total, c->fitness, keys)
+#define GA_REP_CASE(MM)                                                         \
+  case MM:                                                                      \
+    if (need == kNeedSQ) GA_REP_NEED(MM, kNeedSQ);                              \
+    else if (need == kNeedABS) GA_REP_NEED(MM, kNeedABS);                       \
+    else if (need == kNeedNNZ) GA_REP_NEED(MM, kNeedNNZ);                       \
+    else GA_REP_NEED(MM, kNeedSQ | kNeedNNZ);                                   \
+    break;
+    GA_REP_CASE(4) GA_REP_CASE(8) GA_REP_CASE(12) GA_REP_CASE(16)
+    GA_REP_CASE(20) GA_REP_CASE(24) GA_REP_CASE(28) GA_REP_CASE(32)
+#undef GA_REP_NEED
+#undef GA_REP_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -9,10 +9,14 @@
 
 namespace ga {
 
+constexpr uint32_t kFusedTiles = 1024;  // tiles of kSelTile keys
+
 // ---------------------------------------------------------------------------
 // Selection of the `count` smallest (key, index) (elitism; the paper's
 // truncation, Sec. 3.3): a two-level radix select on 12-bit digits of the
-// 24-bit keys, then a stable compaction in index order.
+// 24-bit keys, then a stable compaction in index order.  Four launches up to
+// kFusedTiles tiles of keys, six above; each kernel boundary orders the
+// passes, so no pass needs fences, acquire loads or last-block counters.
 // ---------------------------------------------------------------------------
 struct SelArgs {
   uint32_t* pop_a;   // generation g is in the "a" buffers iff g is even
@@ -37,16 +41,16 @@ __device__ __forceinline__ bool sel_generation(const SelArgs& a, uint32_t* G) {
 }
 
 // Finds the bin holding the target-th element (1-based) of a 4096-bin
-// histogram; returns (bin, count before bin).  Clears the histogram.
-__device__ void scan_find(uint32_t* hist, uint32_t target, uint32_t* bin_out,
-                          uint32_t* before_out) {
+// histogram; returns (bin, count before bin) through LDS.  With `clear`,
+// zeroes the histogram after reading it.
+__device__ void scan_find(uint32_t* hist, uint32_t target, bool clear,
+                          uint32_t* bin_out, uint32_t* before_out) {
   const int per = 4096 / kBlock;  // 16 bins per thread
   uint32_t v[per];
   uint32_t sum = 0;
 #pragma unroll
   for (int i = 0; i < per; ++i) {
-    v[i] = __hip_atomic_load(&hist[threadIdx.x * per + i], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+    v[i] = hist[threadIdx.x * per + i];
     sum += v[i];
   }
   uint32_t total;
@@ -58,10 +62,12 @@ __device__ void scan_find(uint32_t* hist, uint32_t target, uint32_t* bin_out,
       *before_out = run;
     }
     run += v[i];
-    hist[threadIdx.x * per + i] = 0;
+    if (clear) hist[threadIdx.x * per + i] = 0;
   }
 }
 
+// Pass 1: histogram of the high 12 bits of the keys (a block's LDS
+// histogram added into h1).  h1 and h2 are zero on entry.
 __global__ __launch_bounds__(kBlock) void sel_hist_hi(SelArgs a) {
   uint32_t G;
   if (!sel_generation(a, &G)) return;
@@ -76,27 +82,25 @@ __global__ __launch_bounds__(kBlock) void sel_hist_hi(SelArgs a) {
   __syncthreads();
   for (int i = threadIdx.x; i < 4096; i += kBlock)
     if (h[i]) atomicAdd(&a.ws->h1[i], h[i]);
-  if (last_block(&a.ws->cnt[0])) {
-    __shared__ uint32_t s_bin, s_before;
-    scan_find(a.ws->h1, a.count, &s_bin, &s_before);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      a.ws->bucket = s_bin;
-      a.ws->below = s_before;
-      a.ws->cnt[0] = 0;
-    }
-  }
 }
 
+// Pass 2: every block finds the bucket (high bits) of the count-th key from
+// h1, then histograms the low 12 bits of the keys in that bucket into h2.
 __global__ __launch_bounds__(kBlock) void sel_hist_lo(SelArgs a) {
   uint32_t G;
   if (!sel_generation(a, &G)) return;
   const uint32_t g = G - 1;
   const uint32_t* keys = (g & 1u) ? a.keys_b : a.keys_a;
-  const uint32_t bucket = ld_acq(&a.ws->bucket);
+  __shared__ uint32_t s_bucket, s_below;
+  scan_find(a.ws->h1, a.count, false, &s_bucket, &s_below);
   __shared__ uint32_t h[4096];
   for (int i = threadIdx.x; i < 4096; i += kBlock) h[i] = 0;
   __syncthreads();
+  const uint32_t bucket = s_bucket;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ws->bucket = bucket;
+    a.ws->below = s_below;
+  }
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < a.n;
        i += gridDim.x * kBlock) {
     const uint32_t k = keys[i];
@@ -105,27 +109,46 @@ __global__ __launch_bounds__(kBlock) void sel_hist_lo(SelArgs a) {
   __syncthreads();
   for (int i = threadIdx.x; i < 4096; i += kBlock)
     if (h[i]) atomicAdd(&a.ws->h2[i], h[i]);
-  if (last_block(&a.ws->cnt[1])) {
-    __shared__ uint32_t s_bin, s_before;
-    const uint32_t below = ld_acq(&a.ws->below);
-    scan_find(a.ws->h2, a.count - below, &s_bin, &s_before);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      a.ws->T = (bucket << 12) | s_bin;
-      a.ws->r = a.count - below - s_before;  // keys equal to T to take
-      a.ws->cnt[1] = 0;
-    }
+}
+
+// One block: the threshold key T and how many keys equal to T to take;
+// clears both histograms for the next selection.
+__global__ __launch_bounds__(kBlock) void sel_find(SelArgs a) {
+  uint32_t G;
+  if (!sel_generation(a, &G)) return;
+  const uint32_t bucket = a.ws->bucket, below = a.ws->below;
+  __shared__ uint32_t s_bin, s_before;
+  scan_find(a.ws->h2, a.count - below, true, &s_bin, &s_before);
+  for (int i = threadIdx.x; i < 4096; i += kBlock) a.ws->h1[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.ws->T = (bucket << 12) | s_bin;
+    a.ws->r = a.count - below - s_before;  // keys equal to T to take
   }
 }
 
-// Per tile of kSelTile keys: how many are < T and == T; the last block
-// turns the per-tile counts into exclusive offsets.
-__global__ __launch_bounds__(kBlock) void sel_count(SelArgs a) {
+// Per tile of kSelTile keys: how many are < T and == T.  With `fused`,
+// every block first finds T and r from h2 itself (block 0 stores them), in
+// place of the one-block sel_find launch.
+__global__ __launch_bounds__(kBlock) void sel_count(SelArgs a, uint32_t fused) {
   uint32_t G;
   if (!sel_generation(a, &G)) return;
   const uint32_t g = G - 1;
   const uint32_t* keys = (g & 1u) ? a.keys_b : a.keys_a;
-  const uint32_t T = ld_acq(&a.ws->T);
+  uint32_t T;
+  if (fused) {
+    const uint32_t bucket = a.ws->bucket, below = a.ws->below;
+    __shared__ uint32_t s_bin, s_before;
+    scan_find(a.ws->h2, a.count - below, false, &s_bin, &s_before);
+    __syncthreads();
+    T = (bucket << 12) | s_bin;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.ws->T = T;
+      a.ws->r = a.count - below - s_before;
+    }
+  } else {
+    T = a.ws->T;
+  }
   const uint32_t base = blockIdx.x * kSelTile;
   uint32_t less = 0, eq = 0;
   for (uint32_t i = base + threadIdx.x; i < min(a.n, base + kSelTile);
@@ -141,30 +164,28 @@ __global__ __launch_bounds__(kBlock) void sel_count(SelArgs a) {
     a.ws->blk_less[blockIdx.x] = tl;
     a.ws->blk_eq[blockIdx.x] = te;
   }
-  if (last_block(&a.ws->cnt[2])) {
-    // exclusive scan over gridDim.x (<= kMaxSelBlocks) tile counts
-    const uint32_t nb = gridDim.x;
-    const uint32_t per = (nb + kBlock - 1) / kBlock;
-    uint32_t sl = 0, se = 0;
-    for (uint32_t i = threadIdx.x * per; i < min(nb, (threadIdx.x + 1) * per);
-         ++i) {
-      sl += __hip_atomic_load(&a.ws->blk_less[i], __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_AGENT);
-      se += __hip_atomic_load(&a.ws->blk_eq[i], __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_AGENT);
-    }
-    uint32_t dummy;
-    uint32_t rl = block_exclusive_scan(sl, &dummy);
-    uint32_t re = block_exclusive_scan(se, &dummy);
-    for (uint32_t i = threadIdx.x * per; i < min(nb, (threadIdx.x + 1) * per);
-         ++i) {
-      const uint32_t xl = a.ws->blk_less[i], xe = a.ws->blk_eq[i];
-      a.ws->blk_less[i] = rl;
-      a.ws->blk_eq[i] = re;
-      rl += xl;
-      re += xe;
-    }
-    if (threadIdx.x == 0) a.ws->cnt[2] = 0;
+}
+
+// One block: the per-tile counts become exclusive offsets, in place.
+__global__ __launch_bounds__(kBlock) void sel_offsets(SelArgs a, uint32_t nb) {
+  uint32_t G;
+  if (!sel_generation(a, &G)) return;
+  const uint32_t per = (nb + kBlock - 1) / kBlock;
+  const uint32_t i0 = min(nb, threadIdx.x * per), i1 = min(nb, i0 + per);
+  uint32_t sl = 0, se = 0;
+  for (uint32_t i = i0; i < i1; ++i) {
+    sl += a.ws->blk_less[i];
+    se += a.ws->blk_eq[i];
+  }
+  uint32_t dummy;
+  uint32_t rl = block_exclusive_scan(sl, &dummy);
+  uint32_t re = block_exclusive_scan(se, &dummy);
+  for (uint32_t i = i0; i < i1; ++i) {
+    const uint32_t xl = a.ws->blk_less[i], xe = a.ws->blk_eq[i];
+    a.ws->blk_less[i] = rl;
+    a.ws->blk_eq[i] = re;
+    rl += xl;
+    re += xe;
   }
 }
 
@@ -195,7 +216,11 @@ __device__ uint32_t perm_inverse(uint64_t seed, uint32_t G, uint32_t D,
 
 // Stable compaction: the selected individuals, in index order, are copied to
 // slots rank (elitism) or pi^-1(rank) (paper mode) of the next generation.
-__global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a) {
+// The block first lists its selected (source, slot) pairs in LDS, then
+// copies the rows together, each lane issuing its loads before its stores.
+// With `fused`, the block sums the per-tile counts before its own tile (in
+// place of the one-block sel_offsets launch) and the grid clears h1 and h2.
+__global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a, uint32_t fused) {
   uint32_t G;
   if (!sel_generation(a, &G)) return;
   const uint32_t g = G - 1;
@@ -204,7 +229,24 @@ __global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a) {
   const uint32_t* pop = odd ? a.pop_b : a.pop_a;
   uint32_t* pout = odd ? a.pop_a : a.pop_b;
   uint32_t* kout = odd ? a.keys_a : a.keys_b;
-  const uint32_t T = ld_acq(&a.ws->T), r = ld_acq(&a.ws->r);
+  const uint32_t T = a.ws->T, r = a.ws->r;
+  uint32_t tile_less, tile_eq;
+  if (fused) {
+    uint32_t sl = 0, se = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kBlock) {
+      sl += a.ws->blk_less[b];
+      se += a.ws->blk_eq[b];
+    }
+    block_exclusive_scan(sl, &tile_less);
+    block_exclusive_scan(se, &tile_eq);
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < 4096; i += gridDim.x * kBlock) {
+      a.ws->h1[i] = 0;
+      a.ws->h2[i] = 0;
+    }
+  } else {
+    tile_less = a.ws->blk_less[blockIdx.x];
+    tile_eq = a.ws->blk_eq[blockIdx.x];
+  }
   constexpr int PER = kSelTile / kBlock;  // 8 consecutive keys per thread
   const uint32_t i0 = blockIdx.x * kSelTile + threadIdx.x * PER;
   uint32_t kk[PER];
@@ -216,29 +258,65 @@ __global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a) {
     ce += (i0 + e < a.n) && kk[e] == T;
   }
   uint32_t dummy;
-  uint32_t lb = block_exclusive_scan(cl, &dummy) + a.ws->blk_less[blockIdx.x];
-  uint32_t eb = block_exclusive_scan(ce, &dummy) + a.ws->blk_eq[blockIdx.x];
+  uint32_t lb = block_exclusive_scan(cl, &dummy) + tile_less;
+  uint32_t eb = block_exclusive_scan(ce, &dummy) + tile_eq;
+  // this thread's selected elements: slots in s_dst, sources in s_src
+  __shared__ uint32_t s_src[kSelTile], s_dst[kSelTile];
+  uint32_t slots[PER];
+  uint32_t mine = 0;
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
     const uint32_t i = i0 + e;
-    if (i >= a.n) break;
-    const bool less = kk[e] < T, eq = kk[e] == T;
-    const bool take = less || (eq && eb < r);
-    if (take && lb + min(eb, r) < a.count) {
-      const uint32_t rho = lb + min(eb, r);
-      const uint32_t slot =
-          a.paper ? perm_inverse(a.seed, G, a.count, rho) : rho;
-      if (slot < a.count) {
-        const uint4* s4 =
-            reinterpret_cast<const uint4*>(pop + (size_t)i * a.mw);
-        uint4* d4 = reinterpret_cast<uint4*>(pout + (size_t)slot * a.mw);
-        for (uint32_t v = 0; v < a.mw / 4; ++v) d4[v] = s4[v];
-        kout[slot] = kk[e];
+    slots[e] = ~0u;
+    if (i < a.n) {
+      const bool less = kk[e] < T, eq = kk[e] == T;
+      const bool take = less || (eq && eb < r);
+      if (take && lb + min(eb, r) < a.count) {
+        const uint32_t rho = lb + min(eb, r);
+        const uint32_t slot = a.paper ? perm_inverse(a.seed, G, a.count, rho) : rho;
+        if (slot < a.count) {
+          slots[e] = slot;
+          ++mine;
+        }
       }
+      lb += less;
+      eb += eq;
     }
-    lb += less;
-    eb += eq;
   }
+  uint32_t total;
+  uint32_t at = block_exclusive_scan(mine, &total);
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    if (slots[e] != ~0u) {
+      s_src[at] = i0 + e;
+      s_dst[at] = slots[e];
+      kout[slots[e]] = kk[e];
+      ++at;
+    }
+  }
+  __syncthreads();
+  const uint32_t w4 = a.mw / 4, items = total * w4;
+  const uint4* src4 = reinterpret_cast<const uint4*>(pop);
+  uint4* dst4 = reinterpret_cast<uint4*>(pout);
+  // word t of the list: row t / w4, word t % w4 of that row
+  auto src_of = [&](uint32_t t) {
+    const uint32_t row = t / w4;
+    return (size_t)s_src[row] * w4 + (t - row * w4);
+  };
+  auto dst_of = [&](uint32_t t) {
+    const uint32_t row = t / w4;
+    return (size_t)s_dst[row] * w4 + (t - row * w4);
+  };
+  uint32_t t = threadIdx.x;
+  for (; t + 3 * kBlock < items; t += 4 * kBlock) {  // four loads, then four stores
+    const uint4 v0 = src4[src_of(t)], v1 = src4[src_of(t + kBlock)];
+    const uint4 v2 = src4[src_of(t + 2 * kBlock)], v3 = src4[src_of(t + 3 * kBlock)];
+    dst4[dst_of(t)] = v0;
+    dst4[dst_of(t + kBlock)] = v1;
+    dst4[dst_of(t + 2 * kBlock)] = v2;
+    dst4[dst_of(t + 3 * kBlock)] = v3;
+  }
+  for (; t < items; t += kBlock) dst4[dst_of(t)] = src4[src_of(t)];
 }
 
 hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
@@ -260,10 +338,15 @@ hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
   a.stop_on_found = d.stop_on_found;
   const uint32_t gh = std::min<uint32_t>(cdiv(d.n, kBlock * 8), 1024);
   const uint32_t gt = cdiv(d.n, kSelTile);
+  // up to kFusedTiles tiles, the threshold search and the tile offsets are
+  // done by every block of the count and scatter launches themselves
+  const uint32_t fused = gt <= kFusedTiles;
   hipLaunchKernelGGL(sel_hist_hi, dim3(gh), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(sel_hist_lo, dim3(gh), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(sel_count, dim3(gt), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(sel_scatter, dim3(gt), dim3(kBlock), 0, s, a);
+  if (!fused) hipLaunchKernelGGL(sel_find, dim3(1), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(sel_count, dim3(gt), dim3(kBlock), 0, s, a, fused);
+  if (!fused) hipLaunchKernelGGL(sel_offsets, dim3(1), dim3(kBlock), 0, s, a, gt);
+  hipLaunchKernelGGL(sel_scatter, dim3(gt), dim3(kBlock), 0, s, a, fused);
   return hipGetLastError();
 }
 

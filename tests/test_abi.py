@@ -62,3 +62,14 @@ def test_binding_rejects_host_tensors():
     cfg = ga.Config(m=8, n=10)
     with pytest.raises(TypeError):
         ga.ga_init_population(cfg, torch.zeros((10, 8, 1), dtype=torch.int32))
+
+
+def test_fitness_repeat_rejects_bad_repeat_counts():
+    """Argument checks run before any device work: no GPU is touched."""
+    L = ga.lib()
+    cfg = ga.Config(m=20, n=40000).c()
+    fake = ctypes.c_void_p(256)            # never dereferenced: rejected first
+    assert L.ga_fitness_repeat(ctypes.byref(cfg), fake, fake, 0, None) == ga.GA_EINVAL
+    assert "reps" in L.ga_last_error().decode()
+    assert L.ga_fitness_repeat(ctypes.byref(cfg), fake, fake, 1 << 30, None) == ga.GA_EINVAL
+    assert L.ga_fitness_repeat(ctypes.byref(cfg), None, fake, 5, None) == ga.GA_EINVAL

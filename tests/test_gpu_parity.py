@@ -39,6 +39,40 @@ def test_fitness_random_all_kinds(m):
         assert np.array_equal(keys_np(keys2), want)
 
 
+@pytest.mark.parametrize("m", ORDERS)
+def test_fitness_repeat_equals_oracle(m):
+    """The repeated whole-population evaluation writes the same keys as one
+    evaluation, for every order, kind and a ragged n."""
+    torch_cuda()
+    n = 2 * 256 + 91
+    announce("fitness repeat", m, n)
+    pop = inputs.random_population(m, n, seed=300 + m)
+    dpop = dev_pop_from_int8(pop)
+    for i, kind in enumerate(KINDS):
+        cfg = ga.Config(m=m, n=n, fitness=kind)
+        keys = empty_keys(cfg)
+        ga.ga_fitness_repeat(cfg, dpop, keys, reps=1 + 2 * (i % 3))
+        want = gao.fitness(to_oracle(cfg), pop)
+        assert np.array_equal(keys_np(keys), want), kind
+
+
+def test_fitness_repeat_full_size_m20_n40000():
+    """The kernel-metric configuration: m=20, n=40,000, SQ and ABS keys of
+    the seed-1 initial population, evaluated 1000 times."""
+    torch_cuda()
+    announce("fitness repeat m20 n40000")
+    for kind in (ga.FIT_SQ, ga.FIT_ABS):
+        cfg = ga.Config(m=20, n=40000, seed=1, fitness=kind)
+        dpop = empty_pop(cfg)
+        ga.ga_init_population(cfg, dpop)
+        keys = empty_keys(cfg)
+        ga.ga_fitness_repeat(cfg, dpop, keys, reps=1000)
+        want = gao.fitness(to_oracle(cfg), int8_from_dev_pop(dpop, cfg.m))
+        assert np.array_equal(keys_np(keys), want), kind
+        opop = gao.init_population(to_oracle(cfg))
+        assert np.array_equal(int8_from_dev_pop(dpop, cfg.m), opop)
+
+
 def test_fitness_known_hadamard_and_census():
     torch_cuda()
     for m in hf.ORDERS_WITH_FIXTURE:
@@ -146,6 +180,23 @@ def test_step_variants(m, n, t, elite, kind):
                     xo_threshold=ga.rate_threshold(3, 4), mut_threshold=ga.rate_threshold(1, 3),
                     nc=3, nr=2)
     _step_chain(cfg, 4)
+
+
+@pytest.mark.parametrize("m,n,elite,paper", [
+    (8, 2_200_001, 30_000, False),     # more than 1024 selection tiles
+    (4, 4 * 600_000, 0, True),
+])
+def test_step_selection_many_tiles(m, n, elite, paper):
+    """Selection over more than 1024 tiles of 2048 keys takes the unfused
+    pipeline (separate threshold and offset launches)."""
+    torch_cuda()
+    announce("step many tiles", m, n, elite, paper)
+    if paper:
+        cfg = ga.Config(m=m, n=n, seed=13, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
+                        xo_threshold=1 << 32, mut_threshold=1 << 32, nc=1, nr=1)
+    else:
+        cfg = ga.Config(m=m, n=n, seed=12, elite=elite, fitness=ga.FIT_SQ)
+    _step_chain(cfg, 2)
 
 
 def test_step_elite_with_ties():
