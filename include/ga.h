@@ -83,7 +83,12 @@ typedef enum {
 } ga_selection_kind;
 
 enum {
-  GA_STOP_ON_FOUND = 1u  /* ga_run: stop at the first generation with key 0 */
+  GA_STOP_ON_FOUND = 1u, /* ga_run: stop at the first generation with key 0 */
+  /* Lanes per child in the children kernel (the tile shape), bits 8..11 of
+   * flags: 0 lets the library's tuning table choose; 2, 4 or 8 force it
+   * (orders 36..64: 4 or 8).  Results do not depend on it.                 */
+  GA_LANES_SHIFT = 8u,
+  GA_LANES_MASK = 0xF00u
 };
 
 typedef struct {
@@ -100,7 +105,7 @@ typedef struct {
   uint32_t nc;              /* mutated columns per mutated child, <= 64      */
   uint32_t nr;              /* row pairs per mutated child, <= 64            */
   uint32_t max_generations; /* generation budget of ga_run                   */
-  uint32_t flags;           /* GA_STOP_ON_FOUND                              */
+  uint32_t flags;           /* GA_STOP_ON_FOUND | lanes << GA_LANES_SHIFT    */
 } ga_config;
 
 typedef struct {

@@ -30,6 +30,12 @@ GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_EBUDGET, GA_ENOTFOUND = -1, -2, -3, -4, -5
 FIT_SQ, FIT_ABS, FIT_NNZ, FIT_SQ_PLUS_NNZ, FIT_F1, FIT_F2 = range(6)
 SEL_TOURNAMENT, SEL_PAPER = 0, 1
 STOP_ON_FOUND = 1
+LANES_SHIFT = 8
+
+
+def lanes_flag(lanes: int) -> int:
+    """flags bits forcing the children kernel's lanes per child (0: tuned)."""
+    return lanes << LANES_SHIFT
 
 
 class GAError(RuntimeError):

@@ -33,16 +33,6 @@ def sources() -> list[str]:
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _device_asm(src: str) -> str:
-    """Device assembly of one source (gfx950), for the no-calls check."""
-    out = os.path.join(OBJ, os.path.basename(src)[:-4] + ".gfx950.s")
-    r = subprocess.run([HIPCC, *FLAGS, "--cuda-device-only", "-S", src, "-o", out],
-                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc -S failed on {src}:\n{r.stdout}")
-    return out
-
-
 def check_no_calls(asm_path: str) -> None:
     """Every kernel must be call-free and use no scratch memory.  A body the
     compiler outlines into a function longer than a conditional branch can
@@ -65,33 +55,38 @@ def check_no_calls(asm_path: str) -> None:
                 raise RuntimeError(f"{asm_path}: kernel {name} uses scratch memory ({line})")
 
 
-def _compile(src: str) -> tuple[str, float]:
-    obj = os.path.join(OBJ, os.path.basename(src)[:-4] + ".o")
+def _compile(src: str) -> tuple[str, str, float]:
+    """Compiles one source; keeps the compiler's intermediate files in a
+    folder of its own, among them the device assembly the checks read."""
+    base = os.path.basename(src)[:-4]
+    tmp = os.path.join(OBJ, base)
+    os.makedirs(tmp, exist_ok=True)
+    obj = os.path.join(tmp, base + ".o")
     t0 = time.time()
-    r = subprocess.run([HIPCC, *FLAGS, "-c", src, "-o", obj],
-                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    r = subprocess.run([HIPCC, *FLAGS, "-save-temps=obj", "-c", src, "-o", obj],
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, cwd=tmp)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}")
-    return obj, time.time() - t0
+    asm = os.path.join(tmp, f"{base}-hip-amdgcn-amd-amdhsa-{ARCH}.s")
+    if not os.path.exists(asm):
+        raise RuntimeError(f"no device assembly for {src}")
+    return obj, asm, time.time() - t0
 
 
 def build(verbose: bool = True) -> str:
     """Compiles every source (always) and links libga.so; returns its path."""
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
-    kernel_srcs = [s for s in srcs if "__global__" in open(s).read()]
     with cf.ThreadPoolExecutor(max_workers=8) as ex:
-        fut_obj = [ex.submit(_compile, s) for s in srcs]
-        fut_asm = [ex.submit(_device_asm, s) for s in kernel_srcs]
-        results = [f.result() for f in fut_obj]
-        for f in fut_asm:
-            check_no_calls(f.result())
+        results = list(ex.map(_compile, srcs))
+    for _, asm, _ in results:
+        check_no_calls(asm)
     if verbose:
-        for obj, dt in results:
+        for obj, _, dt in results:
             print(f"  compiled {os.path.basename(obj)} in {dt:.1f}s", flush=True)
     tmp = LIB + f".tmp{os.getpid()}"
     r = subprocess.run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}",
-                        *[o for o, _ in results], "-o", tmp],
+                        *[o for o, _, _ in results], "-o", tmp],
                        stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}")

@@ -69,8 +69,13 @@ ga_status validate(const ga_config* c) {
     set_error("nc=%u nr=%u: need 1..64 when mutation is on", c->nc, c->nr);
     return GA_EINVAL;
   }
-  if (c->flags & ~(uint32_t)GA_STOP_ON_FOUND) {
+  if (c->flags & ~(uint32_t)(GA_STOP_ON_FOUND | GA_LANES_MASK)) {
     set_error("unknown flags 0x%x", c->flags);
+    return GA_EINVAL;
+  }
+  const uint32_t lanes = (c->flags & GA_LANES_MASK) >> GA_LANES_SHIFT;
+  if (lanes != 0 && !lanes_allowed(c->m, lanes)) {
+    set_error("lanes=%u: need 2, 4 or 8 for m <= 32, 4 or 8 for m >= 36", lanes);
     return GA_EINVAL;
   }
   if (c->selection == GA_SEL_TOURNAMENT) {
@@ -167,7 +172,9 @@ PopDesc make_desc(const ga_config* c, uint32_t* pa, uint32_t* pb,
   d.max_gen = max_gen;
   d.stop_on_found = stop_on_found;
   d.block_begin = 0;
-  const uint32_t per_block = c->m <= 32 ? kQuadChildren : kOctChildren;
+  d.lanes_forced = forced_lanes(c) ? 1u : 0u;
+  d.lanes = forced_lanes(c) ? forced_lanes(c) : tuned_lanes(c->m, d.nchild);
+  const uint32_t per_block = children_per_block(d.lanes);
   d.nblocks = (d.nchild + per_block - 1) / per_block;
   return d;
 }

@@ -58,7 +58,8 @@ struct PopDesc {
   uint32_t stop_on_found;
   uint32_t block_begin;  // first block of this population in the launch
   uint32_t nblocks;      // blocks of this population
-  uint32_t pad;
+  uint32_t lanes;        // lanes per child in the children kernel
+  uint32_t lanes_forced; // 1: lanes come from the config, not the table
 };
 
 // Workspace of the selection pipeline of one population.
@@ -89,8 +90,8 @@ hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
                          uint32_t node, hipStream_t s);
 // children of every population in descs (device array), all of order m
 hipError_t launch_children(const PopDesc* descs_dev, const uint32_t* block_pop,
-                           uint32_t total_blocks, uint32_t m, uint32_t node,
-                           hipStream_t s);
+                           uint32_t total_blocks, uint32_t m, uint32_t lanes,
+                           uint32_t node, hipStream_t s);
 // children of one population (descriptor passed by value)
 hipError_t launch_children_one(const PopDesc& d, uint32_t node, hipStream_t s);
 // gen_base += k for every population of the table
@@ -106,6 +107,20 @@ hipError_t launch_reset_state(RunState* st, hipStream_t s);
 hipError_t launch_set_state(RunState* st, uint32_t gen, hipStream_t s);
 hipError_t launch_check(const ga_config* c, const uint32_t* pop,
                         uint32_t* bad, hipStream_t s);
+
+// ---- lanes per child (the children kernel's tile shape) -------------------
+// 2, 4 or 8 for orders up to 32 (one word per column); 4 or 8 above.
+inline bool lanes_allowed(uint32_t m, uint32_t lanes) {
+  return m <= 32 ? (lanes == 2 || lanes == 4 || lanes == 8)
+                 : (lanes == 4 || lanes == 8);
+}
+// The tuning table's choice for a launch of `children` children of order m.
+uint32_t tuned_lanes(uint32_t m, uint64_t children);
+// Forced lanes of a config (0 if the table decides).
+inline uint32_t forced_lanes(const ga_config* c) {
+  return (c->flags & GA_LANES_MASK) >> GA_LANES_SHIFT;
+}
+inline uint32_t children_per_block(uint32_t lanes) { return 64 / lanes; }
 
 // ---- helpers (ga_api.hip) -----------------------------------------------
 void set_error(const char* fmt, ...);
@@ -157,6 +172,7 @@ class MultiLaunch {
  private:
   struct Group {
     uint32_t m = 0;                  // order
+    uint32_t lanes = 0;              // lanes per child of the group's launch
     PopDesc* desc = nullptr;
     uint32_t* map = nullptr;
     size_t cap_desc = 0, cap_map = 0;

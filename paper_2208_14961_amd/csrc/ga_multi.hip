@@ -69,9 +69,22 @@ ga_status MultiLaunch::set(const PopDesc* descs, uint32_t count,
     g.m = 4u * (gi + 1);
     std::vector<PopDesc> ds;
     std::vector<uint32_t> map;
+    // one lanes-per-child choice per group: forced by a run's config if any
+    // run of the order forces it, else the tuning table's for the group's
+    // total children (they share one launch)
+    uint64_t children = 0;
+    uint32_t forced = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+      if (group_of(descs[i].m) != gi) continue;
+      children += descs[i].nchild;
+      if (!forced && descs[i].lanes_forced) forced = descs[i].lanes;
+    }
+    g.lanes = forced ? forced : (children ? tuned_lanes(g.m, children) : 0);
     for (uint32_t i = 0; i < count; ++i) {
       if (group_of(descs[i].m) != gi) continue;
       PopDesc d = descs[i];
+      d.lanes = g.lanes;
+      d.nblocks = (d.nchild + children_per_block(g.lanes) - 1) / children_per_block(g.lanes);
       d.block_begin = (uint32_t)map.size();
       for (uint32_t b = 0; b < d.nblocks; ++b)
         map.push_back((uint32_t)ds.size());
@@ -107,7 +120,7 @@ ga_status MultiLaunch::set(const PopDesc* descs, uint32_t count,
 ga_status MultiLaunch::enqueue_generation(uint32_t node, hipStream_t s) {
   for (Group& g : groups_)
     if (g.nblocks)
-      GA_TRY(launch_children(g.desc, g.map, g.nblocks, g.m, node, s),
+      GA_TRY(launch_children(g.desc, g.map, g.nblocks, g.m, g.lanes, node, s),
              "children kernel");
   return GA_OK;
 }
@@ -148,7 +161,7 @@ ga_status MultiLaunch::launch_chunk(uint32_t gens, hipStream_t s) {
       hipStream_t b = branch_[gi];
       st = hip_status(hipStreamWaitEvent(b, fork_[kOrders], 0), "hipStreamWaitEvent");
       for (uint32_t i = 0; i < gens && st == GA_OK; ++i)
-        st = hip_status(launch_children(gr.desc, gr.map, gr.nblocks, gr.m, i, b),
+        st = hip_status(launch_children(gr.desc, gr.map, gr.nblocks, gr.m, gr.lanes, i, b),
                         "children kernel");
       if (st == GA_OK)
         st = hip_status(launch_advance(gr.desc, gr.ndesc, gens, b),

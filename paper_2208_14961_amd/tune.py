@@ -1,0 +1,104 @@
+"""Autotuner of the children kernel's tile shape: lanes per child.
+
+For every order m = 4..64 and a ladder of population sizes, times each
+allowed lanes-per-child variant (2, 4, 8 up to m = 32; 4, 8 above) over a
+run of the plain GA (binary tournament, SQ key, the library's event-timed
+generation loop) and writes the fastest per (order, size) as the tuning
+table `csrc/ga_tuned.h`.  The variants compute identical generations; only
+their speed differs.  Needs a GPU; rebuild the library afterwards.
+
+    python -m paper_2208_14961_amd.tune --out paper_2208_14961_amd/csrc/ga_tuned.h
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+# table columns: launches of up to MAX_CHILDREN[j] children use entry j; each
+# is timed at the size SIZES[j]
+MAX_CHILDREN = [2048, 8192, 32768, 131072, None]
+SIZES = [1024, 4096, 16384, 65536, 262144]
+ORDERS = list(range(4, 65, 4))
+
+
+def lanes_options(m: int):
+    return (2, 4, 8) if m <= 32 else (4, 8)
+
+
+def time_variant(m: int, n: int, lanes: int, gens: int) -> float:
+    """Mean generation time (ms) of a `gens`-generation run."""
+    import torch
+    import paper_2208_14961_amd as ga
+    cfg = ga.Config(m=m, n=n, seed=1, fitness=ga.FIT_SQ, max_generations=gens, flags=ga.lanes_flag(lanes))
+    sh = ga.pop_shape(cfg)
+    bufs = [torch.zeros(sh, dtype=torch.int32, device="cuda") for _ in range(2)]
+    keys = [torch.zeros((n,), dtype=torch.int32, device="cuda") for _ in range(2)]
+    ga.ga_run(cfg, bufs[0], bufs[1], keys[0], keys[1])  # warm
+    best = None
+    for _ in range(3):
+        ga.ga_timing_enable(True)
+        ga.ga_run(cfg, bufs[0], bufs[1], keys[0], keys[1])
+        ms, _ = ga.ga_timing_read()
+        ga.ga_timing_enable(False)
+        best = ms if best is None else min(best, ms)
+    return best
+
+
+def header(table, times) -> str:
+    rows = []
+    for i, m in enumerate(ORDERS):
+        cells = ", ".join(str(table[m][j]) for j in range(len(SIZES)))
+        detail = "; ".join(
+            f"n={SIZES[j]}: " + " ".join(f"L{L} {times[m][j][L] * 1e3:.1f}us"
+                                         for L in lanes_options(m))
+            for j in range(len(SIZES)))
+        rows.append(f"  {{{cells}}},  // m = {m}: {detail}")
+    limits = ", ".join(str(c) if c is not None else "~0ull" for c in MAX_CHILDREN)
+    return f"""// ga_tuned.h -- lanes per child of the children kernel, per order and
+// launch size, as chosen by paper_2208_14961_amd/tune.py on one MI355X
+// (mean generation time of a plain-GA run, binary tournament, SQ key; the
+// times of every variant are in the comments).  Row i is order 4(i+1);
+// entry j applies up to kTuneMaxChildren[j] children.  Regenerate with
+// `python -m paper_2208_14961_amd.tune` on the GPU, then rebuild.
+#pragma once
+#include <stdint.h>
+
+namespace ga {{
+
+constexpr int kTuneSizes = {len(SIZES)};
+constexpr uint64_t kTuneMaxChildren[kTuneSizes] = {{{limits}}};
+constexpr uint8_t kTunedLanes[16][kTuneSizes] = {{
+{chr(10).join(rows)}
+}};
+
+}}  // namespace ga
+"""
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=os.path.join(HERE, "csrc", "ga_tuned.h"))
+    ap.add_argument("--gens", type=int, default=128)
+    args = ap.parse_args()
+    table, times = {}, {}
+    for m in ORDERS:
+        table[m], times[m] = [], []
+        for n in SIZES:
+            t = {L: time_variant(m, n, L, args.gens) for L in lanes_options(m)}
+            best = min(t, key=t.get)
+            table[m].append(best)
+            times[m].append(t)
+            print(f"m={m} n={n}: " + " ".join(f"L{L}={v * 1e3:.2f}us" for L, v in t.items())
+                  + f" -> {best}", flush=True)
+    text = header(table, times)
+    with open(args.out, "w") as f:
+        f.write(text)
+    print(f"wrote {args.out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -39,6 +39,8 @@ def test_population_words():
     dict(xo_threshold=(1 << 32) + 1), dict(mut_threshold=(1 << 32) + 1), dict(nc=0),
     dict(nr=0), dict(nc=65), dict(flags=2), dict(selection=ga.SEL_PAPER, n=10),
     dict(selection=ga.SEL_PAPER, n=12, elite=1),
+    dict(flags=ga.lanes_flag(3)), dict(flags=ga.lanes_flag(1)), dict(flags=ga.lanes_flag(16)),
+    dict(m=36, flags=ga.lanes_flag(2)),
 ])
 def test_invalid_configs(kw):
     base = dict(m=8, n=10)
@@ -53,7 +55,10 @@ def test_valid_configs():
                 ga.Config(m=32, n=200000, elite=2000, fitness=ga.FIT_SQ_PLUS_NNZ),
                 ga.Config(m=12, n=4000, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
                           xo_threshold=1 << 32, mut_threshold=1 << 32, nc=1, nr=2),
-                ga.Config(m=8, n=10, mut_threshold=0, nc=0, nr=0)]:
+                ga.Config(m=8, n=10, mut_threshold=0, nc=0, nr=0),
+                ga.Config(m=8, n=10, flags=ga.lanes_flag(2)),
+                ga.Config(m=32, n=10, flags=ga.STOP_ON_FOUND | ga.lanes_flag(8)),
+                ga.Config(m=64, n=10, flags=ga.lanes_flag(4))]:
         assert ga.ga_validate(cfg), cfg
 
 

@@ -164,6 +164,23 @@ def test_step_tournament(m):
     _step_chain(cfg, 3)
 
 
+LANES = [(m, L) for m in ORDERS for L in ((2, 4, 8) if m <= 32 else (4, 8))]
+
+
+@pytest.mark.parametrize("m,lanes", LANES)
+def test_step_lanes(m, lanes):
+    """Every lanes-per-child variant of the children kernel gives the
+    oracle's generation (the tile shape never changes a result)."""
+    torch_cuda()
+    n = 2 * 128 + 45
+    announce("step lanes", m, lanes, n)
+    cfg = ga.Config(m=m, n=n, seed=500 + m + lanes, elite=m % 3,
+                    fitness=KINDS[(m // 4 + lanes) % len(KINDS)],
+                    mut_threshold=ga.rate_threshold(1, 2), nc=1 + lanes % 3, nr=1 + m % 2,
+                    flags=ga.lanes_flag(lanes))
+    _step_chain(cfg, 2)
+
+
 @pytest.mark.parametrize("m,n,t,elite,kind", [
     (8, 1024, 2, 0, ga.FIT_SQ),
     (12, 999, 3, 7, ga.FIT_NNZ),
@@ -297,13 +314,20 @@ def test_run_batch_equals_single_runs():
         assert np.array_equal(got["matrix"], opop[want["index"]])
 
 
-def test_run_batch_every_order():
+@pytest.mark.parametrize("lanes", ["tuned", "fewest", "most"])
+def test_run_batch_every_order(lanes):
     """One run of every order 4..64 in one batched launch sequence: each
-    order has its own batched children kernel."""
+    order has its own batched children kernel, with the tuned, the fewest
+    or the most lanes per child."""
     torch_cuda()
     kinds = [ga.FIT_SQ, ga.FIT_ABS, ga.FIT_NNZ, ga.FIT_SQ_PLUS_NNZ, ga.FIT_F1, ga.FIT_F2]
+
+    def flags(m):
+        if lanes == "tuned":
+            return 0
+        return ga.lanes_flag((2 if m <= 32 else 4) if lanes == "fewest" else 8)
     cfgs = [ga.Config(m=m, n=200 + 37 * i, seed=7_000_000 + m, fitness=kinds[i % 6],
-                      max_generations=4 + i % 5, flags=0, nc=1 + i % 2, nr=1 + i % 3)
+                      max_generations=4 + i % 5, flags=flags(m), nc=1 + i % 2, nr=1 + i % 3)
             for i, m in enumerate(ORDERS)]
     announce("batch every order", len(cfgs))
     batch = ga.ga_run_batch(cfgs)
