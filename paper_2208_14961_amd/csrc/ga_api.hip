@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -105,6 +106,7 @@ struct Workspace {
   RunState* host_state = nullptr;  // pinned mirrors for polling (two slots)
   hipStream_t capture = nullptr;   // stream the generation graphs run on
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_t[2] = {nullptr, nullptr};  // timing of tuning chunks
   // cached graph of one chunk of generations, valid for `graph_key`
   hipGraphExec_t graph = nullptr;
   std::vector<char> graph_key;
@@ -135,6 +137,7 @@ static ga_status workspace(hipStream_t s, Workspace** out) {
   for (auto& e : w->ev)
     GA_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming),
            "hipEventCreate");
+  for (auto& e : w->ev_t) GA_TRY(hipEventCreate(&e), "hipEventCreate");
   // the histograms and counters start at zero; the kernels restore zeros
   GA_TRY(hipMemset(w->sel, 0, sizeof(SelWork)), "hipMemset(selection)");
   g_ws[key] = w;
@@ -188,6 +191,40 @@ struct Timing {
   uint64_t gens = 0;
 };
 static Timing g_timing;
+
+// Lanes per child measured by earlier runs, per launch shape.
+struct TuneKey {
+  uint32_t m, n, elite, kind, selection, t, nc, nr;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(m, n, elite, kind, selection, t, nc, nr) <
+           std::tie(o.m, o.n, o.elite, o.kind, o.selection, o.t, o.nc, o.nr);
+  }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, uint32_t> g_tuned;
+
+static TuneKey tune_key(const ga_config* c, const PopDesc&) {
+  return TuneKey{c->m, c->n, c->elite, c->fitness, c->selection, c->tournament_k, c->nc, c->nr};
+}
+static bool tuned_lookup(const TuneKey& k, uint32_t* lanes) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(k);
+  if (it == g_tuned.end()) return false;
+  *lanes = it->second;
+  return true;
+}
+static void tuned_store(const TuneKey& k, uint32_t lanes) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[k] = lanes;
+}
+static std::vector<uint32_t> lanes_candidates(uint32_t m) {
+  return m <= 32 ? std::vector<uint32_t>{2, 4, 8} : std::vector<uint32_t>{4, 8};
+}
+static void set_lanes(PopDesc* d, uint32_t lanes) {
+  d->lanes = lanes;
+  const uint32_t per = children_per_block(lanes);
+  d->nblocks = (d->nchild + per - 1) / per;
+}
 
 static uint32_t select_count(const ga_config* c) {
   if (c->selection == GA_SEL_PAPER) return c->n / 2;
@@ -353,31 +390,84 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
   // while chunk k+1 runs; launches past the end of the run return at once.
   const uint32_t chunk = std::min<uint32_t>(64, std::max<uint32_t>(1, cfg->max_generations));
   const uint32_t nchunks = (cfg->max_generations + chunk - 1) / chunk;
-  if (nchunks > 0) {
+  auto capture = [&](const PopDesc& dd) -> ga_status {
     std::vector<char> key(sizeof(PopDesc) + sizeof(ga_config));
-    memcpy(key.data(), &d, sizeof(PopDesc));
+    memcpy(key.data(), &dd, sizeof(PopDesc));
     memcpy(key.data() + sizeof(PopDesc), cfg, sizeof(ga_config));
-    if (!w->graph || w->graph_key != key) {
-      if (w->graph) {
-        GA_TRY(hipGraphExecDestroy(w->graph), "hipGraphExecDestroy");
-        w->graph = nullptr;
-      }
-      hipGraph_t g;
-      GA_TRY(hipStreamBeginCapture(w->capture, hipStreamCaptureModeThreadLocal),
-             "hipStreamBeginCapture");
-      for (uint32_t i = 0; i < chunk && st == GA_OK; ++i)
-        st = enqueue_generation(cfg, d, w, i, w->capture);
-      if (st == GA_OK)
-        st = hip_status(launch_advance_one(w->state, chunk, w->capture),
-                        "advance kernel");
-      hipError_t ce = hipStreamEndCapture(w->capture, &g);
-      if (st != GA_OK) return st;
-      GA_TRY(ce, "hipStreamEndCapture");
-      GA_TRY(hipGraphInstantiate(&w->graph, g, nullptr, nullptr, 0),
-             "hipGraphInstantiate");
-      GA_TRY(hipGraphDestroy(g), "hipGraphDestroy");
-      w->graph_key = key;
+    if (w->graph && w->graph_key == key) return GA_OK;
+    if (w->graph) {
+      GA_TRY(hipGraphExecDestroy(w->graph), "hipGraphExecDestroy");
+      w->graph = nullptr;
     }
+    hipGraph_t g;
+    GA_TRY(hipStreamBeginCapture(w->capture, hipStreamCaptureModeThreadLocal),
+           "hipStreamBeginCapture");
+    ga_status cs = GA_OK;
+    for (uint32_t i = 0; i < chunk && cs == GA_OK; ++i)
+      cs = enqueue_generation(cfg, dd, w, i, w->capture);
+    if (cs == GA_OK)
+      cs = hip_status(launch_advance_one(w->state, chunk, w->capture), "advance kernel");
+    hipError_t ce = hipStreamEndCapture(w->capture, &g);
+    if (cs != GA_OK) return cs;
+    GA_TRY(ce, "hipStreamEndCapture");
+    GA_TRY(hipGraphInstantiate(&w->graph, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    GA_TRY(hipGraphDestroy(g), "hipGraphDestroy");
+    w->graph_key = key;
+    return GA_OK;
+  };
+  // Lanes per child: forced by the config, or measured on this run's own
+  // first chunks (every variant makes the same generations) and remembered
+  // for later runs of the same shape, or, for runs too short to measure,
+  // the tuning table's.
+  const TuneKey tkey = tune_key(cfg, d);
+  const std::vector<uint32_t> cands = lanes_candidates(cfg->m);
+  bool explore = false;
+  if (!forced_lanes(cfg)) {
+    uint32_t known = 0;
+    if (tuned_lookup(tkey, &known)) set_lanes(&d, known);
+    else explore = nchunks >= 2 * cands.size() + 1;
+  }
+  uint32_t first = 0;    // chunks already run
+  bool finished = false;  // the run ended inside those chunks
+  if (nchunks > 0) {
+    // the capture stream starts after the work already enqueued on s
+    GA_TRY(hipEventRecord(w->ev[2], s), "hipEventRecord");
+    GA_TRY(hipStreamWaitEvent(w->capture, w->ev[2], 0), "hipStreamWaitEvent");
+  }
+  if (explore) {
+    float best_ms = 0;
+    uint32_t best = d.lanes;
+    for (uint32_t ci = 0; ci < cands.size() && !finished; ++ci) {
+      set_lanes(&d, cands[ci]);
+      st = capture(d);
+      if (st != GA_OK) return st;
+      // one chunk to settle (a new graph's first launch, caches), one timed
+      for (int rep = 0; rep < 2 && !finished; ++rep) {
+        GA_TRY(hipEventRecord(w->ev_t[0], w->capture), "hipEventRecord");
+        GA_TRY(hipGraphLaunch(w->graph, w->capture), "hipGraphLaunch");
+        GA_TRY(hipEventRecord(w->ev_t[1], w->capture), "hipEventRecord");
+        GA_TRY(hipMemcpyAsync(&w->host_state[0], w->state, sizeof(RunState),
+                              hipMemcpyDeviceToHost, w->capture),
+               "hipMemcpyAsync(state)");
+        GA_TRY(hipStreamSynchronize(w->capture), "hipStreamSynchronize");
+        ++first;
+        finished = run_done(w->host_state[0], cfg->max_generations, stop_on_found);
+        if (rep == 1) {
+          float ms = 0;
+          GA_TRY(hipEventElapsedTime(&ms, w->ev_t[0], w->ev_t[1]), "hipEventElapsedTime");
+          if (ci == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = cands[ci];
+          }
+        }
+      }
+    }
+    if (!finished) tuned_store(tkey, best);  // a measurement cut short is not kept
+    set_lanes(&d, best);
+  }
+  if (first < nchunks && !finished) {
+    st = capture(d);
+    if (st != GA_OK) return st;
     // the capture stream starts after the work already enqueued on s
     GA_TRY(hipEventRecord(w->ev[2], s), "hipEventRecord");
     GA_TRY(hipStreamWaitEvent(w->capture, w->ev[2], 0), "hipStreamWaitEvent");
@@ -390,9 +480,9 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
       GA_TRY(hipEventRecord(w->ev[k & 1], w->capture), "hipEventRecord");
       return GA_OK;
     };
-    st = launch_chunk(0);
+    st = launch_chunk(first);
     if (st != GA_OK) return st;
-    for (uint32_t k = 0; k < nchunks; ++k) {
+    for (uint32_t k = first; k < nchunks; ++k) {
       if (k + 1 < nchunks) {
         st = launch_chunk(k + 1);
         if (st != GA_OK) return st;
@@ -403,7 +493,7 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     }
     if (g_timing.on) {
       // the chunks launched after the stop condition return at once; the
-      // mean is over the generations the run made
+      // mean is over the generations made inside the timed chunks
       GA_TRY(hipEventRecord(g_timing.stop, w->capture), "hipEventRecord");
       GA_TRY(hipEventSynchronize(g_timing.stop), "hipEventSynchronize");
       float ms = 0;
@@ -413,9 +503,12 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
                                ? w->host_state[0] : w->host_state[1];
       uint32_t made = std::min(cfg->max_generations, hs.gen_base);
       if (stop_on_found && hs.found_gen < made) made = hs.found_gen;
+      const uint32_t before = std::min(cfg->max_generations, first * chunk);
       g_timing.total_ms += ms;
-      g_timing.gens += made;
+      g_timing.gens += made > before ? made - before : 0;
     }
+  }
+  if (nchunks > 0) {
     // s continues after everything the capture stream did
     GA_TRY(hipEventRecord(w->ev[2], w->capture), "hipEventRecord");
     GA_TRY(hipStreamWaitEvent(s, w->ev[2], 0), "hipStreamWaitEvent");

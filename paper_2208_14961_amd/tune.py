@@ -18,10 +18,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
-# table columns: launches of up to MAX_CHILDREN[j] children use entry j; each
-# is timed at the size SIZES[j]
-MAX_CHILDREN = [2048, 8192, 32768, 131072, None]
-SIZES = [1024, 4096, 16384, 65536, 262144]
+# table columns: each entry is timed at the population size SIZES[j] and
+# applies to launches of up to MAX_CHILDREN[j] children, the geometric
+# midpoint to the next size (the last entry has no limit)
+SIZES = [1024, 2048, 4096, 8192, 16384, 32768, 49152, 65536, 131072, 262144]
+MAX_CHILDREN = [int((a * b) ** 0.5) for a, b in zip(SIZES, SIZES[1:])] + [None]
 ORDERS = list(range(4, 65, 4))
 
 

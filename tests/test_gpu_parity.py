@@ -287,6 +287,20 @@ def test_run_parity(cfg):
     _same_run(cfg)
 
 
+@pytest.mark.parametrize("cfg", [
+    ga.Config(m=20, n=1500, seed=31, max_generations=400, flags=0),
+    ga.Config(m=40, n=400, seed=32, elite=5, fitness=ga.FIT_ABS, max_generations=300, flags=0),
+])
+def test_run_tunes_lanes_inside_the_run(cfg):
+    """A run long enough to measure every lanes-per-child variant on its own
+    first chunks, then one that reuses the measured choice: both equal the
+    oracle's run."""
+    torch_cuda()
+    announce("run tuned twice", cfg)
+    _same_run(cfg)
+    _same_run(cfg)
+
+
 # --------------------------------------------------------------------------
 # Batched runs and the server
 # --------------------------------------------------------------------------
