@@ -157,7 +157,7 @@ def workload_pmc(args):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "children_m20_n40000_traffic.md")
-TRAFFIC_SOURCES = ["paper_2208_14961_amd/csrc/ga_children.hip",
+TRAFFIC_SOURCES = ["paper_2208_14961_amd/csrc/ga_children.h",
                    "paper_2208_14961_amd/csrc/ga_device.h"]
 
 
@@ -258,8 +258,11 @@ def bench_default(args):
     ga.ga_timing_enable(False)
     achieved = n * ops_per_eval(m, ga.FIT_SQ) / (mean_ms * 1e-3) / 1e12
     peak = alu_peak_tops(m, ga.FIT_SQ)
+    kernel = f"children_one_kernel<20, 1u, {ga.ga_tuned_lanes(cfg)}>"
     tr = measured_traffic()
-    traffic = None if tr is None else tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
+    # the counters hold for the variant they were taken on
+    traffic = (tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
+               if tr is not None and tr.get("kernel") == kernel else None)
     out = {
         "metric": "Gram+fitness evals/s and generations/s at m=20,pop=40k; p50/p99 time-to-solve",
         "value": args.steps * evals / dt,
@@ -279,7 +282,7 @@ def bench_default(args):
         "generations_per_s": args.steps * G / dt,
         "abs_keyed": {"value": args.steps * evals / dt_abs, "unit": "evals/s",
                       "generations_per_s": args.steps * G / dt_abs},
-        "roofline": {"bound": "alu", "kernel": "children_one_kernel<20, SQ>",
+        "roofline": {"bound": "alu", "kernel": kernel,
                      "achieved": achieved, "peak": peak, "unit": "TOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "frac_of_simple_op_peak": achieved / SIMPLE_OP_TOPS,

@@ -144,6 +144,14 @@ ga_status ga_fitness(const ga_config* cfg, const uint32_t* pop,
                      uint32_t* keys, uint32_t* comps, void* stream);
 
 /*
+ * Lanes per child that ga_run would use now for this configuration (the
+ * children kernel's tile shape): the forced value, else the one measured by
+ * an earlier run of the same shape in this process, else the tuning
+ * table's.  0 if the configuration is invalid.  Host only.
+ */
+uint32_t ga_tuned_lanes(const ga_config* cfg);
+
+/*
  * The same Gram + fitness (Sec. 3.2), evaluated `reps` times over the whole
  * population inside one launch: a throughput form of ga_fitness for
  * measuring the Gram + fitness core without per-launch overhead.  Async.

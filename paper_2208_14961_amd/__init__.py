@@ -118,6 +118,7 @@ def lib() -> ctypes.CDLL:
             "ga_init_population": (i32, [P(_Config), vp, vp]),
             "ga_fitness": (i32, [P(_Config), vp, vp, vp, vp]),
             "ga_fitness_repeat": (i32, [P(_Config), vp, vp, u32, vp]),
+            "ga_tuned_lanes": (u32, [P(_Config)]),
             "ga_step": (i32, [P(_Config), vp, vp, vp, vp, u32, vp]),
             "ga_run": (i32, [P(_Config), vp, vp, vp, vp, P(_Result), vp]),
             "ga_run_batch": (i32, [P(_Config), u32, P(_Result), vp]),
@@ -189,6 +190,11 @@ def ga_fitness(cfg: Config, pop, keys, comps=None, stream=None) -> None:
     cp = _dev(comps, (cfg.n, 3), "comps") if comps is not None else None
     _check(lib().ga_fitness(ctypes.byref(cfg.c()), _dev(pop, pop_shape(cfg), "pop"),
                             _dev(keys, (cfg.n,), "keys"), cp, _stream(stream)))
+
+
+def ga_tuned_lanes(cfg: Config) -> int:
+    """Lanes per child ga_run would use now for cfg (0 if cfg is invalid)."""
+    return int(lib().ga_tuned_lanes(ctypes.byref(cfg.c())))
 
 
 def ga_fitness_repeat(cfg: Config, pop, keys, reps: int, stream=None) -> None:

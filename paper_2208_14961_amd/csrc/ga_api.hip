@@ -313,6 +313,15 @@ ga_status ga_fitness(const ga_config* cfg, const uint32_t* pop,
   return GA_OK;
 }
 
+uint32_t ga_tuned_lanes(const ga_config* cfg) {
+  if (validate(cfg) != GA_OK) return 0;
+  if (forced_lanes(cfg)) return forced_lanes(cfg);
+  PopDesc d = make_desc(cfg, nullptr, nullptr, nullptr, nullptr, nullptr,
+                        cfg->max_generations, 0);
+  uint32_t known = 0;
+  return tuned_lookup(tune_key(cfg, d), &known) ? known : d.lanes;
+}
+
 ga_status ga_fitness_repeat(const ga_config* cfg, const uint32_t* pop,
                             uint32_t* keys, uint32_t reps, void* stream) {
   ga_status st = validate(cfg);

@@ -78,3 +78,32 @@ def test_fitness_repeat_rejects_bad_repeat_counts():
     assert "reps" in L.ga_last_error().decode()
     assert L.ga_fitness_repeat(ctypes.byref(cfg), fake, fake, 1 << 30, None) == ga.GA_EINVAL
     assert L.ga_fitness_repeat(ctypes.byref(cfg), None, fake, 5, None) == ga.GA_EINVAL
+
+
+def test_tuning_table_is_well_formed():
+    """The committed lanes-per-child table: one row per order, allowed
+    lanes only, increasing size limits with an open last entry."""
+    import re
+    path = os.path.join(os.path.dirname(ga.LIB_PATH), "csrc", "ga_tuned.h")
+    text = open(path).read()
+    sizes = int(re.search(r"kTuneSizes = (\d+);", text).group(1))
+    limits = re.search(r"kTuneMaxChildren\[kTuneSizes\] = \{([^}]*)\}", text).group(1)
+    limits = [x.strip() for x in limits.split(",")]
+    assert len(limits) == sizes and limits[-1] == "~0ull"
+    nums = [int(x) for x in limits[:-1]]
+    assert nums == sorted(nums) and len(set(nums)) == len(nums)
+    rows = re.findall(r"^\s*\{([0-9, ]+)\},\s*// m = (\d+)", text, re.M)
+    assert [int(m) for _, m in rows] == list(range(4, 65, 4))
+    for cells, m in rows:
+        lanes = [int(x) for x in cells.split(",")]
+        assert len(lanes) == sizes
+        allowed = {2, 4, 8} if int(m) <= 32 else {4, 8}
+        assert set(lanes) <= allowed, (m, lanes)
+
+
+def test_tuned_lanes_query():
+    """Forced lanes are returned as given; otherwise an allowed value."""
+    assert ga.ga_tuned_lanes(ga.Config(m=8, n=100, flags=ga.lanes_flag(2))) == 2
+    assert ga.ga_tuned_lanes(ga.Config(m=20, n=40000)) in (2, 4, 8)
+    assert ga.ga_tuned_lanes(ga.Config(m=64, n=50000)) in (4, 8)
+    assert ga.ga_tuned_lanes(ga.Config(m=6, n=100)) == 0
