@@ -16,8 +16,8 @@ constexpr int kChildBlock = 64;             // one wave per block: children
 constexpr int kQuadChildren = 16;           // children per block, orders <= 32
 constexpr int kOctChildren = 8;             // children per block, orders >= 36
 constexpr int kOrders = 16;                 // orders 4, 8, .., 64
-constexpr int kSelTile = 2048;              // elements per block, selection
-constexpr int kMaxSelBlocks = 8192;         // kMaxN / kSelTile
+constexpr int kSelTile = 512;               // elements per block, selection
+constexpr int kMaxSelBlocks = kMaxN / kSelTile;
 
 // Device-resident progress of one run.  Generation g of the run lives in
 // buffer A if g is even, B if odd.  Launches are issued in chunks: launch i

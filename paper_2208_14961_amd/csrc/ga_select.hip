@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a, uint32_t fused)
     tile_less = a.ws->blk_less[blockIdx.x];
     tile_eq = a.ws->blk_eq[blockIdx.x];
   }
-  constexpr int PER = kSelTile / kBlock;  // 8 consecutive keys per thread
+  constexpr int PER = kSelTile / kBlock;  // consecutive keys per thread
   const uint32_t i0 = blockIdx.x * kSelTile + threadIdx.x * PER;
   uint32_t kk[PER];
   uint32_t cl = 0, ce = 0;
@@ -336,7 +336,7 @@ hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
   a.node = node;
   a.max_gen = d.max_gen;
   a.stop_on_found = d.stop_on_found;
-  const uint32_t gh = std::min<uint32_t>(cdiv(d.n, kBlock * 8), 1024);
+  const uint32_t gh = std::min<uint32_t>(cdiv(d.n, kSelTile), 1024);
   const uint32_t gt = cdiv(d.n, kSelTile);
   // up to kFusedTiles tiles, the threshold search and the tile offsets are
   // done by every block of the count and scatter launches themselves

@@ -204,7 +204,7 @@ def test_step_variants(m, n, t, elite, kind):
     (4, 4 * 600_000, 0, True),
 ])
 def test_step_selection_many_tiles(m, n, elite, paper):
-    """Selection over more than 1024 tiles of 2048 keys takes the unfused
+    """Selection over more than 1024 tiles of 512 keys takes the unfused
     pipeline (separate threshold and offset launches)."""
     torch_cuda()
     announce("step many tiles", m, n, elite, paper)
