@@ -27,17 +27,6 @@ __device__ __forceinline__ unsigned long long block_min_u64(
   return v;
 }
 
-// Minimum of a 64-bit value over the wave; valid in every lane.
-__device__ __forceinline__ unsigned long long wave_min_u64(
-    unsigned long long v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const unsigned long long o = __shfl_xor(v, off, 64);
-    v = o < v ? o : v;
-  }
-  return v;
-}
-
 // Stop-on-found bookkeeping: a wave whose smallest (key, slot) has key 0
 // records generation G as holding a solution.  Rare, so one atomic.
 __device__ __forceinline__ void note_zero(RunState* st,

@@ -307,7 +307,7 @@ __device__ __forceinline__ uint32_t fitness_w2(const uint32_t* P, uint32_t M,
   return key_of(kind, s);
 }
 
-// Load / store one packed individual (M*W words, a multiple of 4) with
+// Load one packed individual (M*W words, a multiple of 4) with
 // 16-byte accesses.
 template <int M>
 __device__ __forceinline__ void load_cols(const uint32_t* src, Cols<M>& c) {
@@ -324,41 +324,6 @@ __device__ __forceinline__ void load_cols(const uint32_t* src, Cols<M>& c) {
   }
 }
 
-template <int M>
-__device__ __forceinline__ void store_cols(uint32_t* dst, const Cols<M>& c) {
-  constexpr int W = Cols<M>::W;
-  uint4* d4 = reinterpret_cast<uint4*>(dst);
-  const uint32_t* flat = &c.w[0][0];
-#pragma unroll
-  for (int v = 0; v < M * W / 4; ++v)
-    d4[v] = make_uint4(flat[4 * v + 0], flat[4 * v + 1], flat[4 * v + 2],
-                       flat[4 * v + 3]);
-}
-
-// Column-exchange crossover while loading (Sec. 3.4): column j of the child
-// comes from `first` if j < cut, else from `second`.
-template <int M>
-__device__ __forceinline__ void load_crossed(const uint32_t* first,
-                                             const uint32_t* second,
-                                             uint32_t cut, Cols<M>& c) {
-  constexpr int W = Cols<M>::W;
-  const uint4* f4 = reinterpret_cast<const uint4*>(first);
-  const uint4* s4 = reinterpret_cast<const uint4*>(second);
-  uint32_t* flat = &c.w[0][0];
-#pragma unroll
-  for (int v = 0; v < M * W / 4; ++v) {
-    const uint4 a = f4[v];
-    const uint4 b = s4[v];
-    const uint32_t av[4] = {a.x, a.y, a.z, a.w};
-    const uint32_t bv[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int j = (4 * v + e) / W;  // column of this word
-      flat[4 * v + e] = ((uint32_t)j < cut) ? av[e] : bv[e];
-    }
-  }
-}
-
 // (a == J) ? x : 0, with the comparison kept opaque to the compiler: a
 // column chosen at run time is then updated by a select per column instead
 // of the indexed scratch access the compiler would otherwise emit.
@@ -370,35 +335,6 @@ __device__ __forceinline__ uint32_t pick_if_eq(uint32_t a, uint32_t x) {
       : "v"(a), "n"(J), "v"(x)
       : "vcc");
   return r;
-}
-
-// Pair-flip mutation (Sec. 3.5, third method) of child ordinal q in
-// generation G, register-resident (M <= 32), any number of columns: nc
-// columns, nr row pairs shared by the columns; a pair is negated only when
-// its two entries differ, so the column stays balanced.  The column is read
-// and written back through per-column selects (no indexed access).
-template <int M>
-__device__ __forceinline__ void mutate(Cols<M>& c, uint64_t seed, uint32_t G,
-                                       uint32_t q, uint32_t nc, uint32_t nr) {
-  static_assert(M <= 32, "register path holds one word per column");
-  DrawSeq ds(seed, kStreamMutate, G, q);
-  for (uint32_t jc = 0; jc < nc; ++jc) {
-    const uint32_t col = 1u + bounded(ds.at(jc), M - 1);
-    uint32_t v = 0;
-    [&]<int... J>(std::integer_sequence<int, J...>) __attribute__((always_inline)) {
-      ((v |= pick_if_eq<J + 1>(col, c.w[J + 1][0])), ...);
-    }(std::make_integer_sequence<int, M - 1>{});
-    uint32_t mask = 0;
-    for (uint32_t ir = 0; ir < nr; ++ir) {
-      const uint32_t r1 = bounded(ds.at(nc + 2 * ir), M);
-      const uint32_t r2 = bounded(ds.at(nc + 2 * ir + 1), M);
-      const uint32_t x = v ^ mask;
-      if (((x >> r1) ^ (x >> r2)) & 1u) mask ^= (1u << r1) | (1u << r2);
-    }
-    [&]<int... J>(std::integer_sequence<int, J...>) __attribute__((always_inline)) {
-      ((c.w[J + 1][0] ^= pick_if_eq<J + 1>(col, mask)), ...);
-    }(std::make_integer_sequence<int, M - 1>{});
-  }
 }
 
 }  // namespace ga
