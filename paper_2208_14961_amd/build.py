@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libga.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
-    "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+    "-O3", "-std=c++20", f"--offload-arch={ARCH}", "-fPIC",
     "-Wall", "-Wno-unused-function",
     # no packed fp32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

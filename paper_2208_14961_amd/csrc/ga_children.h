@@ -101,14 +101,15 @@ __device__ __forceinline__ uint32_t tournament(const PopDesc& d, uint32_t G,
   return bx;
 }
 
+// The words a lane holds of a child of order M with L lanes per child.
+template <int M, int L_>
+using LaneWords = uint32_t[Lanes<M, L_>::F];
+
 // Pair-flip mutation (Sec. 3.5, third method) of a child held as parts: the
 // lane holding the chosen column flips it; the draws are those of the
 // one-lane form (columns at draws 0 .. nc-1, row pairs after them).  One
 // row pair (r1, r2) on column `col` given the flips `mask` chosen so far;
 // `apply` writes the column back.
-// The words a lane holds of a child of order M with L lanes per child.
-template <int M, int L_>
-using LaneWords = uint32_t[Lanes<M, L_>::F];
 
 template <int M, int L_>
 __device__ __forceinline__ void flip_parts(LaneWords<M, L_>& f,
