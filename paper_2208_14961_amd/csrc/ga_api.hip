@@ -138,8 +138,11 @@ static ga_status workspace(hipStream_t s, Workspace** out) {
     GA_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming),
            "hipEventCreate");
   for (auto& e : w->ev_t) GA_TRY(hipEventCreate(&e), "hipEventCreate");
-  // the histograms and counters start at zero; the kernels restore zeros
+  // the histograms start at zero (the kernels restore zeros); the memset
+  // runs on the null stream, which later work on non-blocking streams does
+  // not wait for, so wait for it here
   GA_TRY(hipMemset(w->sel, 0, sizeof(SelWork)), "hipMemset(selection)");
+  GA_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
   g_ws[key] = w;
   *out = w;
   return GA_OK;

@@ -173,8 +173,10 @@ class MultiLaunch {
   struct Group {
     uint32_t m = 0;                  // order
     uint32_t lanes = 0;              // lanes per child of the group's launch
-    PopDesc* desc = nullptr;
+    PopDesc* desc = nullptr;         // device tables read by the launches
     uint32_t* map = nullptr;
+    PopDesc* hdesc = nullptr;        // pinned staging copies of the tables
+    uint32_t* hmap = nullptr;
     size_t cap_desc = 0, cap_map = 0;
     uint32_t ndesc = 0, nblocks = 0;
   };

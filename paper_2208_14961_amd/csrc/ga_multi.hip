@@ -53,6 +53,8 @@ MultiLaunch::~MultiLaunch() {
   for (Group& g : groups_) {
     if (g.desc) (void)hipFree(g.desc);
     if (g.map) (void)hipFree(g.map);
+    if (g.hdesc) (void)hipHostFree(g.hdesc);
+    if (g.hmap) (void)hipHostFree(g.hmap);
   }
 }
 
@@ -60,6 +62,9 @@ static int group_of(uint32_t m) { return (int)(m / 4) - 1; }
 
 ga_status MultiLaunch::set(const PopDesc* descs, uint32_t count,
                            hipStream_t s) {
+  // s idle: no earlier copy still reads the staging buffers and no earlier
+  // launch still reads the device tables
+  GA_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
   if (graph_) {
     GA_TRY(hipGraphExecDestroy(graph_), "hipGraphExecDestroy");
     graph_ = nullptr;
@@ -93,26 +98,37 @@ ga_status MultiLaunch::set(const PopDesc* descs, uint32_t count,
     g.nblocks = (uint32_t)map.size();
     g.ndesc = (uint32_t)ds.size();
     if (ds.empty()) continue;
+    // The launches on s read these tables, so they are uploaded on s itself
+    // (stream order puts the copy before the launches) from pinned staging
+    // memory.
     if (ds.size() > g.cap_desc) {
       if (g.desc) GA_TRY(hipFree(g.desc), "hipFree");
+      if (g.hdesc) GA_TRY(hipHostFree(g.hdesc), "hipHostFree");
+      g.desc = nullptr;
+      g.hdesc = nullptr;
       g.cap_desc = ds.size() * 2;
-      GA_TRY(hipMalloc(&g.desc, g.cap_desc * sizeof(PopDesc)),
-             "hipMalloc(descs)");
+      GA_TRY(hipMalloc(&g.desc, g.cap_desc * sizeof(PopDesc)), "hipMalloc(descs)");
+      GA_TRY(hipHostMalloc(&g.hdesc, g.cap_desc * sizeof(PopDesc), hipHostMallocDefault),
+             "hipHostMalloc(descs)");
     }
     if (map.size() > g.cap_map) {
       if (g.map) GA_TRY(hipFree(g.map), "hipFree");
+      if (g.hmap) GA_TRY(hipHostFree(g.hmap), "hipHostFree");
+      g.map = nullptr;
+      g.hmap = nullptr;
       g.cap_map = map.size() * 2;
-      GA_TRY(hipMalloc(&g.map, g.cap_map * sizeof(uint32_t)),
-             "hipMalloc(block map)");
+      GA_TRY(hipMalloc(&g.map, g.cap_map * sizeof(uint32_t)), "hipMalloc(block map)");
+      GA_TRY(hipHostMalloc(&g.hmap, g.cap_map * sizeof(uint32_t), hipHostMallocDefault),
+             "hipHostMalloc(block map)");
     }
-    // synchronous copies: the tables change only between ticks
-    GA_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-    GA_TRY(hipMemcpy(g.desc, ds.data(), ds.size() * sizeof(PopDesc),
-                     hipMemcpyHostToDevice),
-           "hipMemcpy(descs)");
-    GA_TRY(hipMemcpy(g.map, map.data(), map.size() * sizeof(uint32_t),
-                     hipMemcpyHostToDevice),
-           "hipMemcpy(block map)");
+    memcpy(g.hdesc, ds.data(), ds.size() * sizeof(PopDesc));
+    memcpy(g.hmap, map.data(), map.size() * sizeof(uint32_t));
+    GA_TRY(hipMemcpyAsync(g.desc, g.hdesc, ds.size() * sizeof(PopDesc),
+                          hipMemcpyHostToDevice, s),
+           "hipMemcpyAsync(descs)");
+    GA_TRY(hipMemcpyAsync(g.map, g.hmap, map.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice, s),
+           "hipMemcpyAsync(block map)");
   }
   return GA_OK;
 }
