@@ -14,6 +14,8 @@ m = 8, n = 1,024 plain GA over 32 seeds.
 the same 24 runs one after another.
 --workload served: a Poisson stream of search requests through the server.
 --workload pmc: a short run for hardware-counter passes (no timing).
+--workload paper_study: the paper's mutation study (generations to the first
+Hadamard matrix over the NC x NR grid at m = 12 and 16) beside its tables.
 """
 from __future__ import annotations
 
@@ -402,16 +404,77 @@ def bench_served(args):
     }
 
 
+# Average iterations to a Hadamard matrix over 10 runs per (NC, NR), rows
+# NR = 1..4, columns NC = 1..4 (Sec. 4.3, Tables 3 and 4); starred m=16
+# cells are averages over the few runs that found one.
+PAPER_TABLES = {
+    12: [[34.2, 35.8, 37.4, 35.8], [32.3, 38.8, 40.5, 43.4],
+         [35.2, 42.6, 47.5, 50.7], [36.3, 46.0, 49.9, 65.7]],
+    16: [[130.1, 119.4, 116.0, 115.5], [121.0, 181.3, 135.0, 168.7],
+         [120.0, 158.1, 165.9, 202.7], [120.2, 166.2, 236.2, 301.6]],
+}
+
+
+def bench_paper_study(args):
+    """The paper's mutation study (Sec. 4.3): its truncation selection with
+    n = 4N (N = 1000 by default), key F2 (or F1), crossover and mutation on
+    every offspring, for m in {12, 16} and NC, NR in 1..4, ten seeds per
+    cell, stopping at the first Hadamard matrix or after `budget`
+    generations."""
+    import statistics
+    import paper_2208_14961_amd as ga
+    budget, seeds, N = 5000, 10, args.study_n
+    kind = {"F1": ga.FIT_F1, "F2": ga.FIT_F2}[args.study_fitness]
+    cells, solved_gens = [], []
+    t0 = time.perf_counter()
+    for m in (12, 16):
+        bufs = buffers(ga.Config(m=m, n=4 * N, selection=ga.SEL_PAPER))
+        for nr in range(1, 5):
+            for nc in range(1, 5):
+                gens = []
+                for seed in range(seeds):
+                    cfg = ga.Config(m=m, n=4 * N, seed=8_000_000 + 1000 * m + seed,
+                                    selection=ga.SEL_PAPER, fitness=kind,
+                                    xo_threshold=1 << 32, mut_threshold=1 << 32,
+                                    nc=nc, nr=nr, max_generations=budget)
+                    r = ga.ga_run(cfg, *bufs)
+                    if r["found"]:
+                        gens.append(r["generation"])
+                solved_gens += gens
+                cells.append({"m": m, "nc": nc, "nr": nr, "solved": len(gens), "runs": seeds,
+                              "mean_generations": statistics.fmean(gens) if gens else None,
+                              "median_generations": statistics.median(gens) if gens else None,
+                              "paper_mean": PAPER_TABLES[m][nr - 1][nc - 1]})
+                print(f"paper study: m={m} NC={nc} NR={nr}: {len(gens)}/{seeds} solved", file=sys.stderr,
+                      flush=True)
+    wall = time.perf_counter() - t0
+    return {
+        "metric": "paper-mode generations to first Hadamard, Sec. 4.3 grid",
+        "value": statistics.fmean(solved_gens) if solved_gens else None,
+        "unit": "generations (mean over solved runs)", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * wall, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"paper mode, N={N} (n=4N), {args.study_fitness}, crossover and mutation always, "
+                               f"m in {{12,16}}, NC,NR in 1..4, {seeds} seeds per cell, "
+                               f"budget {budget} generations"},
+        "cells": cells,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="default",
-                    choices=["default", "batched", "served", "pmc"])
+                    choices=["default", "batched", "served", "pmc", "paper_study"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--study-n", type=int, default=1000,
+                    help="paper_study: N, half the parent count (n = 4N)")
+    ap.add_argument("--study-fitness", default="F2", choices=["F1", "F2"],
+                    help="paper_study: the key")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -423,7 +486,7 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     fn = {"default": bench_default, "batched": bench_batched, "served": bench_served,
-          "pmc": workload_pmc}
+          "pmc": workload_pmc, "paper_study": bench_paper_study}
     out = fn[args.workload](args)
     print(json.dumps(out), flush=True)
 

@@ -287,6 +287,21 @@ def test_run_parity(cfg):
     _same_run(cfg)
 
 
+@pytest.mark.parametrize("m,nc,nr,kind,gens", [
+    (12, 1, 1, ga.FIT_F1, 400), (12, 4, 4, ga.FIT_F2, 150), (16, 1, 4, ga.FIT_F2, 150),
+    (16, 3, 2, ga.FIT_F1, 100),
+])
+def test_run_paper_study_cells(m, nc, nr, kind, gens):
+    """Whole runs in the configuration of the mutation study of Sec. 4.3
+    (n = 4000, crossover and mutation on every offspring), with the study's
+    first seed per order and a shortened budget."""
+    torch_cuda()
+    announce("run paper study cell", m, nc, nr, kind)
+    cfg = ga.Config(m=m, n=4000, seed=8_000_000 + 1000 * m, selection=ga.SEL_PAPER, fitness=kind,
+                    xo_threshold=1 << 32, mut_threshold=1 << 32, nc=nc, nr=nr, max_generations=gens)
+    _same_run(cfg)
+
+
 @pytest.mark.parametrize("cfg", [
     ga.Config(m=20, n=1500, seed=31, max_generations=400, flags=0),
     ga.Config(m=40, n=400, seed=32, elite=5, fitness=ga.FIT_ABS, max_generations=300, flags=0),
