@@ -71,7 +71,7 @@ static int bern(uint32_t u, uint64_t threshold) {
 /* ------------------------------------------------------------------------ */
 int gao_validate(const gao_config* c) {
   if (!c) return -1;
-  if (c->m < 4 || c->m > 64 || c->m % 4 != 0) return -1;
+  if (c->m < 4 || c->m > GAO_MAX_M || c->m % 4 != 0) return -1;
   if (c->n < 2) return -1;
   if (c->fitness > GAO_FIT_F2) return -1;
   if (c->selection > GAO_SEL_PAPER) return -1;
@@ -103,7 +103,7 @@ void gao_gram(uint32_t m, const int8_t* Q, int32_t* G) {
 
 uint32_t gao_fitness_one(uint32_t m, uint32_t kind, const int8_t* Q,
                          uint32_t* comps) {
-  int32_t G[64 * 64];
+  int32_t G[GAO_MAX_M * GAO_MAX_M];
   gao_gram(m, Q, G);
   /* components over the pairs of distinct columns i < j */
   uint32_t sq = 0, ab = 0, nnz = 0;
@@ -305,7 +305,7 @@ static void make_pair(const gao_config* c, uint32_t G, uint32_t p,
                       const int8_t* A, const int8_t* B, int8_t* pop_out,
                       uint32_t* keys_out, uint32_t dst0, uint32_t dst1) {
   const uint32_t m = c->m;
-  int8_t O[2][64 * 64];
+  int8_t O[2][GAO_MAX_M * GAO_MAX_M];
   if (bern(gao_draw(c->seed, GAO_STREAM_XOVER, G, p, 0), c->xo_threshold)) {
     uint32_t cut =
         1 + gao_bounded(gao_draw(c->seed, GAO_STREAM_XOVER, G, p, 1), m - 1);

@@ -57,6 +57,9 @@ enum {
 
 enum { GAO_SEL_TOURNAMENT = 0, GAO_SEL_PAPER = 1 };
 
+/* largest order: Table 2 of the paper times orders up to 100 */
+enum { GAO_MAX_M = 128 };
+
 /* Philox stream tags: partition the draw namespace by purpose */
 enum {
   GAO_STREAM_INIT = 1,
@@ -67,7 +70,7 @@ enum {
 };
 
 typedef struct {
-  uint32_t m;               /* order, multiple of 4, 4..64                  */
+  uint32_t m;               /* order, multiple of 4, 4..GAO_MAX_M           */
   uint32_t n;               /* population size                              */
   uint64_t seed;            /* Philox key                                   */
   uint32_t fitness;         /* GAO_FIT_*                                    */

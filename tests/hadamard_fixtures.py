@@ -76,7 +76,8 @@ def is_hadamard(H: np.ndarray) -> bool:
 
 
 def hadamard(m: int) -> np.ndarray:
-    """A normalized Hadamard matrix of order m (m in 4..64, m % 4 == 0, m != 52)."""
+    """A normalized Hadamard matrix of order m (m % 4 == 0, 4 <= m <= 128;
+    not 52, 92, 100 or 116, which these constructions do not reach)."""
     if m & (m - 1) == 0:
         H = sylvester(m)
     elif _is_prime(m - 1) and (m - 1) % 4 == 3:
@@ -92,4 +93,4 @@ def hadamard(m: int) -> np.ndarray:
     return H
 
 
-ORDERS_WITH_FIXTURE = [m for m in range(4, 65, 4) if m != 52]
+ORDERS_WITH_FIXTURE = [m for m in range(4, 129, 4) if m not in (52, 92, 100, 116)]

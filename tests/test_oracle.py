@@ -101,7 +101,7 @@ def test_m4_census():
     assert seen == {(0, 0, 0): 48, (16, 4, 1): 144, (48, 12, 3): 24}
 
 
-@pytest.mark.parametrize("m", [4, 8, 20, 32, 36, 64])
+@pytest.mark.parametrize("m", [4, 8, 20, 32, 36, 64, 68, 100, 128])
 def test_all_equal_columns_closed_form(m):
     """Columns 1..m-1 identical and balanced: every pair has dot product m."""
     Q = np.ones((m, m), dtype=np.int8)
@@ -113,7 +113,7 @@ def test_all_equal_columns_closed_form(m):
     assert gao.fitness_one(Q, gao.FIT_F2)[0] == 2 * P
 
 
-@pytest.mark.parametrize("m", [8, 12, 20, 28, 32, 44, 64])
+@pytest.mark.parametrize("m", [8, 12, 20, 28, 32, 44, 64, 72, 100, 128])
 def test_fitness_matches_row_space_identity(m):
     """sum_ij (Q^T Q)_ij^2 = sum_rs (Q Q^T)_rs^2 (Frobenius norms agree), so
     SQ = (||Q Q^T||_F^2 - m * m^2) / 2 is computed here from rows only; ABS
@@ -135,7 +135,7 @@ def test_fitness_matches_row_space_identity(m):
 # --------------------------------------------------------------------------
 # Initial population
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("m,n", [(4, 500), (8, 200), (20, 50), (64, 10)])
+@pytest.mark.parametrize("m,n", [(4, 500), (8, 200), (20, 50), (64, 10), (100, 6), (128, 4)])
 def test_init_invariants_and_determinism(m, n):
     cfg = gao.Config(m=m, n=n, seed=11)
     pop = gao.init_population(cfg)
@@ -315,7 +315,8 @@ def _children_consistent(cfg, pop, keys, pop2, keys2, gen_in):
             assert keys2[s] == gao.fitness_one(C, cfg.fitness)[0]
 
 
-@pytest.mark.parametrize("m,n,elite", [(8, 64, 0), (12, 51, 0), (20, 40, 4), (36, 17, 3)])
+@pytest.mark.parametrize("m,n,elite", [(8, 64, 0), (12, 51, 0), (20, 40, 4), (36, 17, 3),
+                                        (100, 9, 1)])
 def test_step_tournament(m, n, elite):
     cfg = gao.Config(m=m, n=n, seed=3, elite=elite, mut_threshold=gao.rate_threshold(1, 2),
                      nc=2, nr=3)
@@ -391,7 +392,7 @@ def test_validate():
     ok = gao.Config(m=8, n=10)
     assert gao.validate(ok)
     bad = [
-        dict(m=6), dict(m=0), dict(m=68), dict(n=1), dict(fitness=6),
+        dict(m=6), dict(m=0), dict(m=132), dict(n=1), dict(fitness=6),
         dict(selection=2), dict(tournament_k=0), dict(elite=10),
         dict(xo_threshold=(1 << 32) + 1), dict(nc=0), dict(nr=0),
         dict(selection=gao.SEL_PAPER, n=10), dict(selection=gao.SEL_PAPER, n=12, elite=1),
@@ -400,6 +401,7 @@ def test_validate():
         c = gao.Config(**{**ok.__dict__, **kw})
         assert not gao.validate(c), kw
     assert gao.validate(gao.Config(m=8, n=10, mut_threshold=0, nc=0, nr=0))
+    assert gao.validate(gao.Config(m=128, n=10)) and gao.validate(gao.Config(m=68, n=10))
 
 
 @pytest.mark.slow
