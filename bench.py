@@ -14,6 +14,8 @@ m = 8, n = 1,024 plain GA over 32 seeds.
 the same 24 runs one after another.
 --workload served: a Poisson stream of search requests through the server.
 --workload pmc: a short run for hardware-counter passes (no timing).
+--workload table2: the paper's timing table (10^4 generations of 40,000
+matrices per order and key) beside its seconds.
 --workload paper_study: the paper's mutation study (generations to the first
 Hadamard matrix over the NC x NR grid at m = 12 and 16) beside its tables.
 """
@@ -415,6 +417,60 @@ PAPER_TABLES = {
 }
 
 
+# Seconds for 10^4 generations of 40,000 matrices (N = 10^4), NC = 4,
+# NR = 2, mean of 10 runs, keys F1 and F2 (Sec. 4.2, Table 2).
+PAPER_TABLE2 = {20: (60.50, 59.38), 40: (103.15, 99.84), 60: (176.28, 170.20),
+                80: (275.92, 256.59), 100: (416.68, 381.38)}
+
+
+def bench_table2(args):
+    """The paper's fitness-function timing (Sec. 4.2, Table 2): paper-mode
+    runs of 10^4 generations over 40,000 matrices (N = 10^4), crossover and
+    mutation on every offspring, NC = 4, NR = 2, keys F1 and F2, for each
+    order of the table the library supports; wall time of a whole run
+    (init, fitness, 10^4 generations), median of `--steps` runs after a
+    warm run."""
+    import statistics
+    import torch
+    import paper_2208_14961_amd as ga
+    N, T = 10_000, 10_000
+    rows = []
+    for m, (p1, p2) in PAPER_TABLE2.items():
+        if m > ga.MAX_ORDER:
+            continue
+        bufs = buffers(ga.Config(m=m, n=4 * N, selection=ga.SEL_PAPER))
+        for name, kind, paper_s in (("F1", ga.FIT_F1, p1), ("F2", ga.FIT_F2, p2)):
+            cfg = ga.Config(m=m, n=4 * N, seed=9_000 + m, selection=ga.SEL_PAPER, fitness=kind,
+                            xo_threshold=1 << 32, mut_threshold=1 << 32, nc=4, nr=2,
+                            max_generations=T, flags=0)
+            ga.ga_run(cfg, *bufs)  # warm: the run's lanes-per-child measurement
+            times = []
+            for _ in range(max(1, args.steps)):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                r = ga.ga_run(cfg, *bufs)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t)
+            sec = statistics.median(times)
+            rows.append({"m": m, "key": name, "seconds": sec, "generations_per_s": T / sec,
+                         "paper_seconds": paper_s, "speedup_vs_paper": paper_s / sec,
+                         "best_key": r["best_key"]})
+            print(f"table2: m={m} {name}: {sec:.3f} s (paper {paper_s} s)", file=sys.stderr,
+                  flush=True)
+    head = next(r for r in rows if r["m"] == 20 and r["key"] == "F2")
+    return {
+        "metric": "paper-mode generations/s, 40,000 matrices, NC=4, NR=2 (Sec. 4.2, Table 2)",
+        "value": head["generations_per_s"], "unit": "generations/s", "n_gpus": 1,
+        "steps": max(1, args.steps), "warmup": 1, "ms_per_step": 1e3 * head["seconds"],
+        "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": head["generations_per_s"] / (T / PAPER_TABLE2[20][1]),
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "paper mode, m=20, N=10^4 (40,000 matrices), F2, NC=4, NR=2, "
+                               "10^4 generations per run, no stop on found"},
+        "rows": rows,
+    }
+
+
 def bench_paper_study(args):
     """The paper's mutation study (Sec. 4.3): its truncation selection with
     n = 4N (N = 1000 by default), key F2 (or F1), crossover and mutation on
@@ -467,7 +523,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="default",
-                    choices=["default", "batched", "served", "pmc", "paper_study"])
+                    choices=["default", "batched", "served", "pmc", "paper_study", "table2"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -486,7 +542,8 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     fn = {"default": bench_default, "batched": bench_batched, "served": bench_served,
-          "pmc": workload_pmc, "paper_study": bench_paper_study}
+          "pmc": workload_pmc, "paper_study": bench_paper_study,
+          "table2": bench_table2}
     out = fn[args.workload](args)
     print(json.dumps(out), flush=True)
 

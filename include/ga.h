@@ -7,9 +7,11 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * Population layout ("packed").  A population of n matrices of order m is an
- * array of uint32 words pop[n][m][W], W = ceil(m / 32).  Column j of matrix
- * k occupies words pop[k][j][0..W-1]; bit (r % 32) of word r / 32 is 1 iff
- * entry (row r, column j) is -1.  Bits for rows >= m are 0.  The paper
+ * array of uint32 words pop[n][m][W], W = 1 for m <= 32, 2 for m <= 64 and
+ * 4 for m <= 128 (above order 64 a column is one 16-byte group; its words
+ * past ceil(m / 32) are 0).  Column j of matrix k occupies words
+ * pop[k][j][0..W-1]; bit (r % 32) of word r / 32 is 1 iff entry (row r,
+ * column j) is -1.  Bits for rows >= m are 0.  The paper
  * stores int8 entries Q[m*m*k + m*i + j] (Sec. 3.4); this layout holds the
  * same matrices with one bit per entry, so that the dot product of two
  * columns is c_i . c_j = m - 2 * popcount(x_i xor x_j).
@@ -84,15 +86,18 @@ typedef enum {
 
 enum {
   GA_STOP_ON_FOUND = 1u, /* ga_run: stop at the first generation with key 0 */
-  /* Lanes per child in the children kernel (the tile shape), bits 8..11 of
-   * flags: 0 lets the library's tuning table choose; 2, 4 or 8 force it
-   * (orders 36..64: 4 or 8).  Results do not depend on it.                 */
+  /* Lanes per child in the children kernel (the tile shape), bits 8..12 of
+   * flags: 0 lets the library's tuning table choose; 2, 4, 8 or 16 force it
+   * (orders 36..64: 4 or 8; orders 68..128: 8 or 16).  Results do not
+   * depend on it.                                                          */
   GA_LANES_SHIFT = 8u,
-  GA_LANES_MASK = 0xF00u
+  GA_LANES_MASK = 0x1F00u
 };
 
+enum { GA_MAX_M = 128 };  /* largest order */
+
 typedef struct {
-  uint32_t m;               /* order: m % 4 == 0, 4 <= m <= 64               */
+  uint32_t m;               /* order: m % 4 == 0, 4 <= m <= GA_MAX_M         */
   uint32_t n;               /* population size (>= 2; paper mode: n = 4N)    */
   uint64_t seed;            /* Philox key                                    */
   uint32_t fitness;         /* ga_fitness_kind                               */
@@ -113,7 +118,8 @@ typedef struct {
   uint32_t generation;  /* generation of the reported population             */
   uint32_t index;       /* slot of its best individual (lowest on ties)      */
   uint32_t best_key;    /* that individual's key                             */
-  int8_t matrix[64 * 64]; /* that individual, int8 +1/-1, row-major m x m   */
+  int8_t matrix[GA_MAX_M * GA_MAX_M]; /* that individual, int8 +1/-1,
+                                         row-major m x m                     */
 } ga_result;
 
 /* Message describing the calling thread's last error ("" if none). */
@@ -122,7 +128,8 @@ const char* ga_last_error(void);
 /* GA_OK iff the configuration is valid (limits as documented above). */
 ga_status ga_validate(const ga_config* cfg);
 
-/* Number of uint32 words of one packed population: n * m * ceil(m / 32). */
+/* Number of uint32 words of one packed population: n * m * W (W as in the
+ * layout above); 0 for an invalid order. */
 size_t ga_population_words(const ga_config* cfg);
 
 /*
@@ -192,7 +199,11 @@ ga_status ga_fitness_repeat(const ga_config* cfg, const uint32_t* pop,
  * parent slots k and k + N exactly as above and writes them to slots
  * 2N + k and 3N + k.
  *
- * Selection ranks keys below 2^24 (all fitness kinds for m <= 64 are).
+ * Elitism and paper mode rank keys below 2^24.  Every kind fits up to
+ * order 76; from order 80 on, the SQ and SQ + NNZ keys of some matrices do
+ * not (the largest SQ key is C(m-1, 2) * m^2), so ga_validate rejects those
+ * kinds with elitism or paper mode there.  Tournaments without elites
+ * compare whole keys and take every kind at every order.
  */
 ga_status ga_step(const ga_config* cfg, const uint32_t* pop_in,
                   const uint32_t* keys_in, uint32_t* pop_out,

@@ -5,10 +5,10 @@ Each function marshals its arguments and calls the C ABI of the same name
 (include/ga.h); every step of the computation runs in libga's HIP kernels.
 Device buffers are torch tensors on a ROCm device:
 
-* a population is an int32 tensor of shape (n, m, W), W = ceil(m / 32),
-  holding the packed uint32 words (bit r of column j set iff entry (r, j)
-  is -1);
-* keys are int32 tensors of shape (n,) (all keys are below 2^24);
+* a population is an int32 tensor of shape (n, m, W), W = col_words(m)
+  (1 up to order 32, 2 up to 64, 4 up to 128), holding the packed uint32
+  words (bit r of column j set iff entry (r, j) is -1);
+* keys are int32 tensors of shape (n,) (all keys are below 2^31);
 * components are int32 tensors of shape (n, 3): (SQ, ABS, NNZ).
 
 Calls are enqueued on torch's current stream unless a stream is given.
@@ -30,7 +30,13 @@ GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_EBUDGET, GA_ENOTFOUND = -1, -2, -3, -4, -5
 FIT_SQ, FIT_ABS, FIT_NNZ, FIT_SQ_PLUS_NNZ, FIT_F1, FIT_F2 = range(6)
 SEL_TOURNAMENT, SEL_PAPER = 0, 1
 STOP_ON_FOUND = 1
+MAX_ORDER = 128  # largest order m the library accepts (GA_MAX_M)
 LANES_SHIFT = 8
+
+
+def col_words(m: int) -> int:
+    """Words per packed column of order m (the layout of include/ga.h)."""
+    return 1 if m <= 32 else (2 if m <= 64 else 4)
 
 
 def lanes_flag(lanes: int) -> int:
@@ -59,7 +65,7 @@ class _Result(ctypes.Structure):
     _fields_ = [
         ("found", ctypes.c_int32), ("generation", ctypes.c_uint32),
         ("index", ctypes.c_uint32), ("best_key", ctypes.c_uint32),
-        ("matrix", ctypes.c_int8 * (64 * 64)),
+        ("matrix", ctypes.c_int8 * (MAX_ORDER * MAX_ORDER)),
     ]
 
 
@@ -89,7 +95,8 @@ class Config:
 
     @property
     def words(self) -> int:
-        return (self.m + 31) // 32
+        """Words per packed column: 1 up to order 32, 2 up to 64, 4 above."""
+        return col_words(self.m)
 
     def c(self) -> _Config:
         return _Config(self.m, self.n, self.seed, self.fitness, self.selection,

@@ -41,15 +41,29 @@ ga_status hip_status(hipError_t e, const char* what) {
     if (_s != GA_OK) return _s;                     \
   } while (0)
 
-uint32_t words_per_col(uint32_t m) { return (m + 31) / 32; }
+uint32_t words_per_col(uint32_t m) { return col_words(m); }
+
+// The largest key of a kind at order m (all columns equal: every pair has
+// |c_i . c_j| = m).
+static uint64_t max_key(uint32_t m, uint32_t kind) {
+  const uint64_t P = (uint64_t)(m - 1) * (m - 2) / 2, mm = m;
+  switch (kind) {
+    case GA_FIT_SQ: return P * mm * mm;
+    case GA_FIT_ABS: return P * mm;
+    case GA_FIT_NNZ: return P;
+    case GA_FIT_SQ_PLUS_NNZ: return P * mm * mm + P;
+    case GA_FIT_F1: return 2 * P * mm;
+    default: return 2 * P;
+  }
+}
 
 ga_status validate(const ga_config* c) {
   if (!c) {
     set_error("config is NULL");
     return GA_EINVAL;
   }
-  if (c->m < 4 || c->m > 64 || c->m % 4) {
-    set_error("m=%u: need m %% 4 == 0 and 4 <= m <= 64", c->m);
+  if (c->m < 4 || c->m > GA_MAX_M || c->m % 4) {
+    set_error("m=%u: need m %% 4 == 0 and 4 <= m <= %u", c->m, (uint32_t)GA_MAX_M);
     return GA_EINVAL;
   }
   if (c->n < 2 || c->n > kMaxN) {
@@ -76,7 +90,8 @@ ga_status validate(const ga_config* c) {
   }
   const uint32_t lanes = (c->flags & GA_LANES_MASK) >> GA_LANES_SHIFT;
   if (lanes != 0 && !lanes_allowed(c->m, lanes)) {
-    set_error("lanes=%u: need 2, 4 or 8 for m <= 32, 4 or 8 for m >= 36", lanes);
+    set_error("lanes=%u: need 2, 4 or 8 for m <= 32, 4 or 8 for m <= 64, 8 or 16 above",
+              lanes);
     return GA_EINVAL;
   }
   if (c->selection == GA_SEL_TOURNAMENT) {
@@ -93,6 +108,13 @@ ga_status validate(const ga_config* c) {
     set_error("paper mode: need n %% 4 == 0 and elite == 0");
     return GA_EINVAL;
   }
+  const bool ranks = c->selection == GA_SEL_PAPER || c->elite > 0;
+  if (ranks && max_key(c->m, c->fitness) >= (1ull << kKeyBits)) {
+    set_error("m=%u: keys of fitness kind %u reach 2^%u, beyond what elitism and paper "
+              "selection rank; use another kind or tournaments without elites",
+              c->m, c->fitness, kKeyBits);
+    return GA_EINVAL;
+  }
   return GA_OK;
 }
 
@@ -107,6 +129,8 @@ struct Workspace {
   hipStream_t capture = nullptr;   // stream the generation graphs run on
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   hipEvent_t ev_t[2] = {nullptr, nullptr};  // timing of tuning chunks
+  uint32_t* perm = nullptr;        // paper mode: a chunk's slot table
+  uint64_t perm_cap = 0;           // its entries
   // cached graph of one chunk of generations, valid for `graph_key`
   hipGraphExec_t graph = nullptr;
   std::vector<char> graph_key;
@@ -221,7 +245,9 @@ static void tuned_store(const TuneKey& k, uint32_t lanes) {
   g_tuned[k] = lanes;
 }
 static std::vector<uint32_t> lanes_candidates(uint32_t m) {
-  return m <= 32 ? std::vector<uint32_t>{2, 4, 8} : std::vector<uint32_t>{4, 8};
+  if (m <= 32) return {2, 4, 8};
+  if (m <= 64) return {4, 8};
+  return {8, 16};
 }
 static void set_lanes(PopDesc* d, uint32_t lanes) {
   d->lanes = lanes;
@@ -236,19 +262,20 @@ static uint32_t select_count(const ga_config* c) {
 
 // Enqueues launch `node` of a chunk for a single population: the
 // selection kernels if the mode needs them, then the children kernel.
+// slots: paper mode's slot table row for this launch, or null.
 static ga_status enqueue_generation(const ga_config* c, const PopDesc& d,
                                     Workspace* w, uint32_t node,
-                                    hipStream_t s) {
+                                    const uint32_t* slots, hipStream_t s) {
   const uint32_t cnt = select_count(c);
   if (cnt > 0)
-    GA_TRY(launch_select(d, cnt, w->sel, node, s), "selection kernels");
+    GA_TRY(launch_select(d, cnt, w->sel, node, slots, s), "selection kernels");
   GA_TRY(launch_children_one(d, node, s), "children kernel");
   return GA_OK;
 }
 
 static void unpack_matrix(uint32_t m, const uint32_t* words, int8_t* out) {
   const uint32_t W = words_per_col(m);
-  memset(out, 0, 64 * 64);
+  memset(out, 0, (size_t)GA_MAX_M * GA_MAX_M);
   for (uint32_t r = 0; r < m; ++r)
     for (uint32_t j = 0; j < m; ++j) {
       const uint32_t bit = (words[j * W + r / 32] >> (r % 32)) & 1u;
@@ -373,7 +400,7 @@ ga_status ga_step(const ga_config* cfg, const uint32_t* pop_in,
                         odd ? keys_out : ki, odd ? ki : keys_out, w->state,
                         0xffffffffu, 0);
   GA_TRY(launch_set_state(w->state, gen_in, s), "state kernel");
-  return enqueue_generation(cfg, d, w, 0, s);
+  return enqueue_generation(cfg, d, w, 0, nullptr, s);
 }
 
 ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
@@ -402,10 +429,29 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
   // while chunk k+1 runs; launches past the end of the run return at once.
   const uint32_t chunk = std::min<uint32_t>(64, std::max<uint32_t>(1, cfg->max_generations));
   const uint32_t nchunks = (cfg->max_generations + chunk - 1) / chunk;
+  // Paper mode: the chunk's slot permutations are computed by one launch at
+  // its start (when the table stays small), not inside each scatter.
+  const uint32_t D = cfg->selection == GA_SEL_PAPER ? cfg->n / 2 : 0;
+  const bool table = D > 0 && nchunks > 0 && (uint64_t)D * chunk <= kMaxPermTable;
+  if (table && w->perm_cap < (uint64_t)D * chunk) {
+    // a cached graph may still run with the old table
+    GA_TRY(hipStreamSynchronize(w->capture), "hipStreamSynchronize");
+    if (w->graph) {
+      GA_TRY(hipGraphExecDestroy(w->graph), "hipGraphExecDestroy");
+      w->graph = nullptr;
+    }
+    if (w->perm) GA_TRY(hipFree(w->perm), "hipFree(slot table)");
+    w->perm = nullptr;
+    w->perm_cap = 0;
+    GA_TRY(hipMalloc(&w->perm, (size_t)D * chunk * sizeof(uint32_t)), "hipMalloc(slot table)");
+    w->perm_cap = (uint64_t)D * chunk;
+  }
   auto capture = [&](const PopDesc& dd) -> ga_status {
-    std::vector<char> key(sizeof(PopDesc) + sizeof(ga_config));
+    std::vector<char> key(sizeof(PopDesc) + sizeof(ga_config) + sizeof(uint32_t*));
+    uint32_t* tab = table ? w->perm : nullptr;
     memcpy(key.data(), &dd, sizeof(PopDesc));
     memcpy(key.data() + sizeof(PopDesc), cfg, sizeof(ga_config));
+    memcpy(key.data() + sizeof(PopDesc) + sizeof(ga_config), &tab, sizeof tab);
     if (w->graph && w->graph_key == key) return GA_OK;
     if (w->graph) {
       GA_TRY(hipGraphExecDestroy(w->graph), "hipGraphExecDestroy");
@@ -415,8 +461,9 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     GA_TRY(hipStreamBeginCapture(w->capture, hipStreamCaptureModeThreadLocal),
            "hipStreamBeginCapture");
     ga_status cs = GA_OK;
+    if (tab) cs = hip_status(launch_perm_table(dd, D, chunk, tab, w->capture), "slot table kernel");
     for (uint32_t i = 0; i < chunk && cs == GA_OK; ++i)
-      cs = enqueue_generation(cfg, dd, w, i, w->capture);
+      cs = enqueue_generation(cfg, dd, w, i, tab ? tab + (size_t)i * D : nullptr, w->capture);
     if (cs == GA_OK)
       cs = hip_status(launch_advance_one(w->state, chunk, w->capture), "advance kernel");
     hipError_t ce = hipStreamEndCapture(w->capture, &g);

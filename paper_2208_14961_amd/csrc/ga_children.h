@@ -1,8 +1,9 @@
 // ga_children.h -- one generation's children: parent selection,
 // column-exchange crossover (Sec. 3.4), pair-flip mutation (Sec. 3.5) and
 // the child's fitness (Sec. 3.2), fused in one kernel with L lanes per child
-// (2, 4 or 8 for orders up to 32; 4 or 8 for orders 36..64).  Templates
-// only: the ga_children_*.hip files instantiate them for their orders.
+// (2, 4 or 8 for orders up to 32; 4 or 8 for orders 36..64; 8 or 16 for
+// orders 68..128).  Templates only: the ga_children_*.hip files instantiate
+// them for their orders.
 // Launch `node` of a chunk produces generation G = gen_base + node + 1 from
 // generation G - 1; a wave that makes a child of fitness 0 lowers the run's
 // found_gen to G.
@@ -17,7 +18,7 @@ namespace ga {
 
 // ---------------------------------------------------------------------------
 // L lanes per child, 2L per child pair; one word per column up to order 32,
-// two above.
+// two up to 64, four (one 16-byte group) above.
 //
 // Lane 2Lg + t of a block works on pair g of the block: child c = t / L,
 // part l = t for child 0 and 2L-1 - t for child 1, so the lanes holding part
@@ -30,7 +31,9 @@ namespace ga {
 // columns.  For the fitness the child is staged in LDS, and lane l takes the
 // column pairs (i, i + d mod C), C = M - 1 odd, d = 1 .. (C-1)/2, for i in
 // its L-th of 0 .. C-1: every unordered pair of columns 1 .. M-1 exactly
-// once.  The child's lanes then add their partial sums.
+// once.  The child's lanes then add their partial sums.  Above order 64 a
+// lane holds its first columns and a sliding window of the partners, one
+// new column per distance (lane_pair_sums_w4).
 // ---------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
@@ -44,11 +47,20 @@ __device__ __forceinline__ U4 quad_bcast(const U4& v) {
   return U4{dpp_mov<C>(v.x), dpp_mov<C>(v.y), dpp_mov<C>(v.z), dpp_mov<C>(v.w)};
 }
 
+// The value of lane 31 - t of each 32 lanes (bitmask swizzle: and 0x1F,
+// or 0, xor 0x1F).
+__device__ __forceinline__ uint32_t mirror32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (0x1F << 10));
+}
+
 template <int M, int L_>
 struct Lanes {
-  static constexpr int W = (M + 31) / 32;      // words per column
+  static constexpr int W = (int)col_words(M);  // words per column
+  static constexpr int WL = (M + 31) / 32;     // of them holding rows
   static constexpr int L = L_;                 // lanes per child
-  static_assert(W == 1 ? (L == 2 || L == 4 || L == 8) : (L == 4 || L == 8),
+  static_assert(W == 1   ? (L == 2 || L == 4 || L == 8)
+                : W == 2 ? (L == 4 || L == 8)
+                         : (L == 8 || L == 16),
                 "lanes per child");
   static constexpr int CPB = 64 / L;           // children per block (one wave)
   static constexpr int P4 = M * W / 4;         // 16-byte groups per individual
@@ -61,15 +73,19 @@ struct Lanes {
     return (s + 1) * L <= P4 || l + (uint32_t)(L * s) < (uint32_t)P4;
   }
   // the sibling lane's value (lane 2L-1 - t of the 2L lanes): quad
-  // permutation [3,2,1,0], half-row mirror or row mirror
+  // permutation [3,2,1,0], half-row mirror, row mirror or 32-lane mirror
   static __device__ __forceinline__ uint32_t mirror(uint32_t v) {
-    return L == 2 ? dpp_mov<0x1B>(v) : (L == 4 ? dpp_mov<0x141>(v) : dpp_mov<0x140>(v));
+    if (L == 2) return dpp_mov<0x1B>(v);
+    if (L == 4) return dpp_mov<0x141>(v);
+    if (L == 8) return dpp_mov<0x140>(v);
+    return mirror32(v);
   }
   // sum over the child's L lanes, in every one of them
   static __device__ __forceinline__ uint32_t sum(uint32_t v) {
-    v += dpp_mov<0xB1>(v);               // lane ^ 1
-    if (L >= 4) v += dpp_mov<0x4E>(v);   // lane ^ 2
-    if (L == 8) v += dpp_mov<0x141>(v);  // the other quad of the eight
+    v += dpp_mov<0xB1>(v);                // lane ^ 1
+    if (L >= 4) v += dpp_mov<0x4E>(v);    // lane ^ 2
+    if (L >= 8) v += dpp_mov<0x141>(v);   // the other quad of the eight
+    if (L == 16) v += dpp_mov<0x140>(v);  // the other eight of the row
     return v;
   }
 };
@@ -138,22 +154,76 @@ __device__ __forceinline__ void flip_parts(LaneWords<M, L_>& f,
   }(std::make_integer_sequence<int, F>{});
 }
 
+// The same for four-word columns (orders above 64): the column is the
+// lane's group col / L, the flips so far a 128-bit mask of four words.
 template <int M, int L_>
-__device__ __forceinline__ void mutate_parts(LaneWords<M, L_>& f,
-                                             uint32_t l, DrawSeq& ds,
-                                             uint32_t nc, uint32_t nr) {
+__device__ __forceinline__ void flip_parts4(LaneWords<M, L_>& f,
+                                            uint32_t l, uint32_t col,
+                                            uint32_t r1, uint32_t r2,
+                                            uint32_t (&mask)[4], bool apply) {
+  using Q = Lanes<M, L_>;
+  constexpr int NP = Q::NP, L = Q::L;
+  const uint32_t grp = col / L;  // the column's group in the lane holding it
+  uint32_t x[4] = {0, 0, 0, 0};
+  [&]<int... S>(std::integer_sequence<int, S...>) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ((x[e] |= pick_if_eq<S>(grp, f[4 * S + e])), ...);
+  }(std::make_integer_sequence<int, NP>{});
+  const U4 y{x[0] ^ mask[0], x[1] ^ mask[1], x[2] ^ mask[2], x[3] ^ mask[3]};
+  const uint32_t b1 = (y[r1 >> 5] >> (r1 & 31u)) & 1u;
+  const uint32_t b2 = (y[r2 >> 5] >> (r2 & 31u)) & 1u;
+  if (b1 != b2) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      mask[e] ^= ((r1 >> 5) == (uint32_t)e ? 1u << (r1 & 31u) : 0u) ^
+                 ((r2 >> 5) == (uint32_t)e ? 1u << (r2 & 31u) : 0u);
+  }
+  if (!apply || col % L != l) return;  // another lane holds the column
+  [&]<int... S>(std::integer_sequence<int, S...>) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ((f[4 * S + e] ^= pick_if_eq<S>(grp, mask[e])), ...);
+  }(std::make_integer_sequence<int, NP>{});
+}
+
+template <int M, int L_>
+__device__ __forceinline__ void mutate_parts4(LaneWords<M, L_>& f,
+                                              uint32_t l, DrawSeq& ds,
+                                              uint32_t nc, uint32_t nr) {
   if (nc == 1 && nr == 1) {  // draws 0, 1, 2: all in the given block 0
-    uint64_t mask = 0;
-    flip_parts<M, L_>(f, l, 1u + bounded(ds.cur.x, M - 1), bounded(ds.cur.y, M),
-                  bounded(ds.cur.z, M), mask, true);
+    uint32_t mask[4] = {0, 0, 0, 0};
+    flip_parts4<M, L_>(f, l, 1u + bounded(ds.cur.x, M - 1), bounded(ds.cur.y, M),
+                       bounded(ds.cur.z, M), mask, true);
     return;
   }
   for (uint32_t jc = 0; jc < nc; ++jc) {
     const uint32_t col = 1u + bounded(ds.at(jc), M - 1);
-    uint64_t mask = 0;
+    uint32_t mask[4] = {0, 0, 0, 0};
     for (uint32_t ir = 0; ir < nr; ++ir)
-      flip_parts<M, L_>(f, l, col, bounded(ds.at(nc + 2 * ir), M),
-                    bounded(ds.at(nc + 2 * ir + 1), M), mask, ir + 1 == nr);
+      flip_parts4<M, L_>(f, l, col, bounded(ds.at(nc + 2 * ir), M),
+                         bounded(ds.at(nc + 2 * ir + 1), M), mask, ir + 1 == nr);
+  }
+}
+
+template <int M, int L_>
+__device__ __forceinline__ void mutate_parts(LaneWords<M, L_>& f,
+                                             uint32_t l, DrawSeq& ds,
+                                             uint32_t nc, uint32_t nr) {
+  if constexpr (Lanes<M, L_>::W == 4) {
+    mutate_parts4<M, L_>(f, l, ds, nc, nr);
+  } else {
+    if (nc == 1 && nr == 1) {  // draws 0, 1, 2: all in the given block 0
+      uint64_t mask = 0;
+      flip_parts<M, L_>(f, l, 1u + bounded(ds.cur.x, M - 1), bounded(ds.cur.y, M),
+                        bounded(ds.cur.z, M), mask, true);
+      return;
+    }
+    for (uint32_t jc = 0; jc < nc; ++jc) {
+      const uint32_t col = 1u + bounded(ds.at(jc), M - 1);
+      uint64_t mask = 0;
+      for (uint32_t ir = 0; ir < nr; ++ir)
+        flip_parts<M, L_>(f, l, col, bounded(ds.at(nc + 2 * ir), M),
+                          bounded(ds.at(nc + 2 * ir + 1), M), mask, ir + 1 == nr);
+    }
   }
 }
 
@@ -196,11 +266,57 @@ __device__ __forceinline__ Sums lane_pair_sums(const uint32_t* me, uint32_t l) {
   return s;
 }
 
+// The same for four-word columns (orders above 64).  Lane l owns columns
+// r + k (k < K, r = l K; past C - 1 a zero column, which adds d = 0 against
+// any balanced partner), and a ring of K partner columns: before distance
+// dd it holds columns r + dd .. r + dd + K - 1, slot t % K for column r + t,
+// so each distance loads one column and every operand index is fixed at
+// compile time.  The distances run in blocks of K, then a tail of D % K.
+template <int M, uint32_t NEED, int L_>
+__device__ __forceinline__ Sums lane_pair_sums_w4(const uint32_t* me, uint32_t l) {
+  using Q = Lanes<M, L_>;
+  constexpr int C = Q::C, D = Q::D, K = Q::K, WL = Q::WL, H = M / 2;
+  const uint4* col = reinterpret_cast<const uint4*>(me) + 1;  // columns 1 .. C
+  const uint32_t r = l * K;
+  uint4 a[K], b[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t i = r + k;
+    b[k] = col[i % C];
+    a[k] = i < (uint32_t)C ? b[k] : make_uint4(0, 0, 0, 0);
+  }
+  uint32_t nxt = (r + K) % C;  // column of ring entry t = dd + K - 1
+  Sums s{0, 0, 0};
+  constexpr int NB = D / K, TAIL = D % K;
+#pragma unroll 1
+  for (int blk = 0; blk < NB; ++blk) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {  // distance dd = blk K + j + 1
+      b[j] = col[nxt];
+      nxt = nxt + 1 == (uint32_t)C ? 0u : nxt + 1;
+#pragma unroll
+      for (int k = 0; k < K; ++k) pair_step4<NEED, WL>(a[k], b[(k + j + 1) % K], H, s);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < TAIL; ++j) {
+    b[j] = col[nxt];
+    nxt = nxt + 1 == (uint32_t)C ? 0u : nxt + 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) pair_step4<NEED, WL>(a[k], b[(k + j + 1) % K], H, s);
+  }
+  return s;
+}
+
 template <int M, uint32_t NEED, int L_>
 __device__ __forceinline__ uint32_t lanes_fitness_need(const uint32_t* me,
                                                        uint32_t l, uint32_t kind) {
   using Q = Lanes<M, L_>;
-  Sums s = lane_pair_sums<M, NEED, L_>(me, l);
+  Sums s;
+  if constexpr (Q::W == 4)
+    s = lane_pair_sums_w4<M, NEED, L_>(me, l);
+  else
+    s = lane_pair_sums<M, NEED, L_>(me, l);
   if (NEED & kNeedSQ) s.sq = Q::sum(s.sq);
   if (NEED & kNeedABS) s.ab = Q::sum(s.ab);
   if (NEED & kNeedNNZ) s.nz = Q::sum(s.nz);
@@ -289,6 +405,15 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d,
     mutate_parts<M, L_>(f, l, ds, d.nc, d.nr);
   }
   uint32_t* me = lds + (g * 2 + c) * MW;
+  uint4* o4 = reinterpret_cast<uint4*>(pout + (size_t)dst * MW);
+  if constexpr (Q::W == 4) {  // store now: the words are dead in the fitness
+    if (valid) {
+#pragma unroll
+      for (int s = 0; s < NP; ++s)
+        if (Q::has(s, l))
+          o4[l + L * s] = make_uint4(f[4 * s], f[4 * s + 1], f[4 * s + 2], f[4 * s + 3]);
+    }
+  }
 #pragma unroll
   for (int s = 0; s < NP; ++s)
     if (Q::has(s, l))
@@ -297,11 +422,12 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d,
   __syncthreads();
   const uint32_t key = lanes_fitness<M, NEED, L_>(me, l, d.kind);
   if (!valid) return ~0ull;
-  uint4* o4 = reinterpret_cast<uint4*>(pout + (size_t)dst * MW);
+  if constexpr (Q::W != 4) {
 #pragma unroll
-  for (int s = 0; s < NP; ++s)
-    if (Q::has(s, l))
-      o4[l + L * s] = make_uint4(f[4 * s], f[4 * s + 1], f[4 * s + 2], f[4 * s + 3]);
+    for (int s = 0; s < NP; ++s)
+      if (Q::has(s, l))
+        o4[l + L * s] = make_uint4(f[4 * s], f[4 * s + 1], f[4 * s + 2], f[4 * s + 3]);
+  }
   if (l == 0) kout[dst] = key;
   return ((unsigned long long)key << 32) | dst;
 }
@@ -360,19 +486,23 @@ __global__ __launch_bounds__(kChildBlock) void children_multi_kernel(
 template <int M, int L>
 hipError_t launch_one_lanes(const PopDesc& d, uint32_t node, hipStream_t s) {
   const dim3 grid(d.nblocks), block(kChildBlock);
-  switch (needs_of_kind(d.kind)) {
-    case kNeedSQ:
-      hipLaunchKernelGGL((children_one_kernel<M, kNeedSQ, L>), grid, block, 0, s, d, node);
-      break;
-    case kNeedABS:
-      hipLaunchKernelGGL((children_one_kernel<M, kNeedABS, L>), grid, block, 0, s, d, node);
-      break;
-    case kNeedNNZ:
-      hipLaunchKernelGGL((children_one_kernel<M, kNeedNNZ, L>), grid, block, 0, s, d, node);
-      break;
-    default:
-      hipLaunchKernelGGL((children_one_kernel<M, kNeedSQ | kNeedNNZ, L>), grid, block, 0,
-                         s, d, node);
+  if constexpr (M > 64) {  // one kernel per tile shape; the kind is chosen inside
+    hipLaunchKernelGGL((children_one_kernel<M, 0u, L>), grid, block, 0, s, d, node);
+  } else {
+    switch (needs_of_kind(d.kind)) {
+      case kNeedSQ:
+        hipLaunchKernelGGL((children_one_kernel<M, kNeedSQ, L>), grid, block, 0, s, d, node);
+        break;
+      case kNeedABS:
+        hipLaunchKernelGGL((children_one_kernel<M, kNeedABS, L>), grid, block, 0, s, d, node);
+        break;
+      case kNeedNNZ:
+        hipLaunchKernelGGL((children_one_kernel<M, kNeedNNZ, L>), grid, block, 0, s, d, node);
+        break;
+      default:
+        hipLaunchKernelGGL((children_one_kernel<M, kNeedSQ | kNeedNNZ, L>), grid, block, 0,
+                           s, d, node);
+    }
   }
   return hipGetLastError();
 }
@@ -381,10 +511,15 @@ hipError_t launch_one_lanes(const PopDesc& d, uint32_t node, hipStream_t s) {
 template <int M>
 hipError_t launch_one_order(const PopDesc& d, uint32_t node, hipStream_t s) {
   switch (d.lanes) {
-    case 4: return launch_one_lanes<M, 4>(d, node, s);
-    case 8: return launch_one_lanes<M, 8>(d, node, s);
     case 2:
       if constexpr (M <= 32) return launch_one_lanes<M, 2>(d, node, s);
+      return hipErrorInvalidValue;
+    case 4:
+      if constexpr (M <= 64) return launch_one_lanes<M, 4>(d, node, s);
+      return hipErrorInvalidValue;
+    case 8: return launch_one_lanes<M, 8>(d, node, s);
+    case 16:
+      if constexpr (M > 64) return launch_one_lanes<M, 16>(d, node, s);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
@@ -397,15 +532,26 @@ hipError_t launch_multi_order(const PopDesc* descs, const uint32_t* block_pop,
                               hipStream_t s) {
   const dim3 grid(blocks), block(kChildBlock);
   switch (lanes) {
-    case 4:
-      hipLaunchKernelGGL((children_multi_kernel<M, 4>), grid, block, 0, s, descs, block_pop, node);
-      break;
-    case 8:
-      hipLaunchKernelGGL((children_multi_kernel<M, 8>), grid, block, 0, s, descs, block_pop, node);
-      break;
     case 2:
       if constexpr (M <= 32) {
         hipLaunchKernelGGL((children_multi_kernel<M, 2>), grid, block, 0, s, descs, block_pop,
+                           node);
+        break;
+      }
+      return hipErrorInvalidValue;
+    case 4:
+      if constexpr (M <= 64) {
+        hipLaunchKernelGGL((children_multi_kernel<M, 4>), grid, block, 0, s, descs, block_pop,
+                           node);
+        break;
+      }
+      return hipErrorInvalidValue;
+    case 8:
+      hipLaunchKernelGGL((children_multi_kernel<M, 8>), grid, block, 0, s, descs, block_pop, node);
+      break;
+    case 16:
+      if constexpr (M > 64) {
+        hipLaunchKernelGGL((children_multi_kernel<M, 16>), grid, block, 0, s, descs, block_pop,
                            node);
         break;
       }
@@ -436,7 +582,8 @@ hipError_t launch_multi_order(const PopDesc* descs, const uint32_t* block_pop,
   }
 #define GA_FOR_EACH_ORDER(X)                                                  \
   X(4) X(8) X(12) X(16) X(20) X(24) X(28) X(32) X(36) X(40) X(44) X(48) X(52) \
-  X(56) X(60) X(64)
+  X(56) X(60) X(64) X(68) X(72) X(76) X(80) X(84) X(88) X(92) X(96) X(100)   \
+  X(104) X(108) X(112) X(116) X(120) X(124) X(128)
 
 GA_FOR_EACH_ORDER(GA_DECLARE_ORDER)
 

@@ -1,5 +1,5 @@
 // ga_children.hip -- dispatch of the children launches to the per-order
-// entry points (ga_children_a..f.hip).
+// entry points (ga_children_a..n.hip).
 #include "ga_children.h"
 
 namespace ga {

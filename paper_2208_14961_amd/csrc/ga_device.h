@@ -2,8 +2,8 @@
 //
 // Counter-based randomness (Philox4x32-10), bounded draws, and the packed
 // Gram + fitness core.  A population is stored packed: column j of a matrix
-// of order M is W = ceil(M/32) uint32 words, bit r set iff entry (r, j) is
-// -1.  The dot product of columns i and j is M - 2 popcount(x_i ^ x_j)
+// of order M is W = col_words(M) uint32 words (1, 2, or 4 above order 64),
+// bit r set iff entry (r, j) is -1.  The dot product of columns i and j is M - 2 popcount(x_i ^ x_j)
 // (Sec. 3.2 uses the Gram matrix Q^T Q of +-1 columns; this is the same
 // number computed on bits).
 #pragma once
@@ -12,6 +12,8 @@
 #include <stdint.h>
 
 #include <utility>
+
+#include "ga_internal.h"
 
 namespace ga {
 
@@ -132,7 +134,7 @@ struct DrawSeq {
 // ---------------------------------------------------------------------------
 template <int M>
 struct Cols {
-  static constexpr int W = (M + 31) / 32;
+  static constexpr int W = (int)col_words(M);
   uint32_t w[M][W];
 };
 
@@ -175,6 +177,23 @@ __device__ __forceinline__ void pair_step(uint32_t x0, uint32_t x1, int W,
   const int d = (W > 1 ? (int)__popc(x0) + (int)__popc(x1) : (int)__popc(x0)) - H;
   if (NEED & kNeedSQ) s.sq = acc_sq(s.sq, d);
   if (NEED & kNeedABS) s.ab = acc_abs(s.ab, (uint32_t)(d + H), (uint32_t)H);
+  if (NEED & kNeedNNZ) s.nz = acc_nz(s.nz, d);
+}
+
+// The same for columns of four words (orders above 64); the first WL words
+// hold rows, the rest are 0.
+template <uint32_t NEED, int WL>
+__device__ __forceinline__ void pair_step4(const uint4& a, const uint4& b, int H,
+                                           Sums& s) {
+  uint32_t p = __popc(a.x ^ b.x) + __popc(a.y ^ b.y) + __popc(a.z ^ b.z);
+  if (WL == 4) p += __popc(a.w ^ b.w);
+  if (NEED == kNeedABS) {
+    s.ab = acc_abs(s.ab, p, (uint32_t)H);
+    return;
+  }
+  const int d = (int)p - H;
+  if (NEED & kNeedSQ) s.sq = acc_sq(s.sq, d);
+  if (NEED & kNeedABS) s.ab = acc_abs(s.ab, p, (uint32_t)H);
   if (NEED & kNeedNNZ) s.nz = acc_nz(s.nz, d);
 }
 
@@ -255,6 +274,46 @@ __device__ __forceinline__ uint32_t key_of(uint32_t kind, const Sums& s) {
   }
 }
 
+// Blocked pair sums of a memory-resident individual of runtime order
+// 68 <= M <= 128 (four words per column), as blocked_sums_w2.
+template <uint32_t NEED, int R>
+__device__ __forceinline__ void load_block4(const uint32_t* P, uint32_t M,
+                                            uint32_t col0, uint4 (&x)[R]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t col = col0 + r;
+    x[r] = col < M ? reinterpret_cast<const uint4*>(P)[col] : make_uint4(0, 0, 0, 0);
+  }
+}
+
+template <uint32_t NEED, int R>
+__device__ __forceinline__ Sums blocked_sums_w4(const uint32_t* P, uint32_t M) {
+  const uint32_t C = M - 1, NB = (C + R - 1) / R;
+  const int H = (int)(M / 2);
+  Sums s{0, 0, 0};
+  for (uint32_t bi = 0; bi < NB; ++bi) {
+    uint4 xi[R];
+    load_block4<NEED, R>(P, M, 1 + bi * R, xi);
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int b = a + 1; b < R; ++b) pair_step4<NEED, 4>(xi[a], xi[b], H, s);
+    for (uint32_t bj = bi + 1; bj < NB; ++bj) {
+      uint4 xj[R];
+      load_block4<NEED, R>(P, M, 1 + bj * R, xj);
+#pragma unroll
+      for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int b = 0; b < R; ++b) pair_step4<NEED, 4>(xi[a], xj[b], H, s);
+    }
+  }
+  const uint32_t npad = NB * R - C, npp = npad * (npad - 1) / 2;
+  s.sq -= npp * (uint32_t)(H * H);
+  s.ab -= npp * (uint32_t)H;
+  s.nz -= npp;
+  return s;
+}
+
 template <uint32_t NEED>
 __device__ __forceinline__ Sums sums_w2(const uint32_t* P, uint32_t M) {
   return M <= 44 ? blocked_sums_w2<NEED, 4>(P, M) : blocked_sums_w2<NEED, 8>(P, M);
@@ -297,6 +356,29 @@ __device__ __forceinline__ uint32_t fitness_w2(const uint32_t* P, uint32_t M,
       case kNeedABS: s = sums_w2<kNeedABS>(P, M); break;
       case kNeedNNZ: s = sums_w2<kNeedNNZ>(P, M); break;
       default: s = sums_w2<kNeedSQ | kNeedNNZ>(P, M); break;
+    }
+  }
+  if (comps) {
+    out3[0] = 4u * s.sq;
+    out3[1] = 2u * s.ab;
+    out3[2] = s.nz;
+  }
+  return key_of(kind, s);
+}
+
+// ... or memory-resident, runtime order 68 <= M <= 128.
+__device__ __forceinline__ uint32_t fitness_w4(const uint32_t* P, uint32_t M,
+                                               uint32_t kind, bool comps,
+                                               uint32_t* out3) {
+  Sums s;
+  if (comps) {
+    s = blocked_sums_w4<kNeedSQ | kNeedABS | kNeedNNZ, 8>(P, M);
+  } else {
+    switch (needs_of_kind(kind)) {
+      case kNeedSQ: s = blocked_sums_w4<kNeedSQ, 8>(P, M); break;
+      case kNeedABS: s = blocked_sums_w4<kNeedABS, 8>(P, M); break;
+      case kNeedNNZ: s = blocked_sums_w4<kNeedNNZ, 8>(P, M); break;
+      default: s = blocked_sums_w4<kNeedSQ | kNeedNNZ, 8>(P, M); break;
     }
   }
   if (comps) {

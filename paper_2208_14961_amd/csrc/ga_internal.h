@@ -8,6 +8,12 @@
 
 namespace ga {
 
+// Words per packed column: 1 up to order 32, 2 up to 64, 4 up to 128 (a
+// column of a larger order is one 16-byte group; its unused words are 0).
+__host__ __device__ constexpr uint32_t col_words(uint32_t m) {
+  return m <= 32 ? 1u : (m <= 64 ? 2u : 4u);
+}
+
 constexpr uint32_t kMaxN = 1u << 24;        // population size limit
 constexpr uint32_t kMaxElite = 1u << 16;    // elite count limit
 constexpr uint32_t kKeyBits = 24;           // selection ranks keys < 2^24
@@ -15,8 +21,9 @@ constexpr int kBlock = 256;                 // threads per block, bulk kernels
 constexpr int kChildBlock = 64;             // one wave per block: children
 constexpr int kQuadChildren = 16;           // children per block, orders <= 32
 constexpr int kOctChildren = 8;             // children per block, orders >= 36
-constexpr int kOrders = 16;                 // orders 4, 8, .., 64
+constexpr int kOrders = GA_MAX_M / 4;       // orders 4, 8, .., 128
 constexpr int kSelTile = 512;               // elements per block, selection
+constexpr uint64_t kMaxPermTable = 1u << 24;  // entries of a chunk's slot table
 constexpr int kMaxSelBlocks = kMaxN / kSelTile;
 
 // Device-resident progress of one run.  Generation g of the run lives in
@@ -85,9 +92,15 @@ hipError_t launch_fitness_repeat(const ga_config* c, const uint32_t* pop,
                                  hipStream_t s);
 // selection of the `count` smallest (key, index) of generation G - 1 into
 // generation G (elitism: slot = rank in index order; paper mode: slot =
-// pi^-1(rank)), G from the state and the launch's node
+// pi^-1(rank)), G from the state and the launch's node.  slots: paper mode's
+// pi^-1 for this launch's generation from launch_perm_table, or null to
+// evaluate it inline.
 hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
-                         uint32_t node, hipStream_t s);
+                         uint32_t node, const uint32_t* slots, hipStream_t s);
+// paper mode: pi^-1 over [0, count) for the generations of launches
+// 0 .. nodes-1 of a chunk, row by row into out[nodes][count]
+hipError_t launch_perm_table(const PopDesc& d, uint32_t count, uint32_t nodes,
+                             uint32_t* out, hipStream_t s);
 // children of every population in descs (device array), all of order m
 hipError_t launch_children(const PopDesc* descs_dev, const uint32_t* block_pop,
                            uint32_t total_blocks, uint32_t m, uint32_t lanes,
@@ -109,10 +122,12 @@ hipError_t launch_check(const ga_config* c, const uint32_t* pop,
                         uint32_t* bad, hipStream_t s);
 
 // ---- lanes per child (the children kernel's tile shape) -------------------
-// 2, 4 or 8 for orders up to 32 (one word per column); 4 or 8 above.
+// 2, 4 or 8 for orders up to 32 (one word per column); 4 or 8 up to 64 (two
+// words); 8 or 16 above (four words).
 inline bool lanes_allowed(uint32_t m, uint32_t lanes) {
-  return m <= 32 ? (lanes == 2 || lanes == 4 || lanes == 8)
-                 : (lanes == 4 || lanes == 8);
+  if (m <= 32) return lanes == 2 || lanes == 4 || lanes == 8;
+  if (m <= 64) return lanes == 4 || lanes == 8;
+  return lanes == 8 || lanes == 16;
 }
 // The tuning table's choice for a launch of `children` children of order m.
 uint32_t tuned_lanes(uint32_t m, uint64_t children);
@@ -180,7 +195,7 @@ class MultiLaunch {
     size_t cap_desc = 0, cap_map = 0;
     uint32_t ndesc = 0, nblocks = 0;
   };
-  Group groups_[kOrders];            // one per order 4, 8, .., 64
+  Group groups_[kOrders];            // one per order 4, 8, .., 128
   hipGraphExec_t graph_ = nullptr;
   uint32_t graph_gens_ = 0;
   hipStream_t capture_ = nullptr;

@@ -3,7 +3,7 @@
 //
 // One lane per individual.  A lane keeps the packed columns of its matrix
 // in registers (orders up to 32) or reads them in register tiles (orders
-// 36..64), so the Gram matrix is never materialized: each off-diagonal
+// 36..128), so the Gram matrix is never materialized: each off-diagonal
 // entry is one xor and one popcount per word, reduced into the key on the
 // fly.
 #include <hip/hip_runtime.h>
@@ -22,30 +22,56 @@ template <int M>
 __global__ __launch_bounds__(kBlock) void init_kernel(uint32_t* pop,
                                                       uint32_t n,
                                                       uint64_t seed) {
-  constexpr int W = (M + 31) / 32;
+  constexpr int W = (int)col_words(M);
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (uint64_t)n * M) return;
   const uint32_t k = (uint32_t)(t / M), j = (uint32_t)(t % M);
-  uint64_t v = 0;
-  if (j > 0) {
-    v = (M / 2 == 64) ? ~0ull : ((1ull << (M / 2)) - 1ull);  // rows < M/2 = -1
-    // Fisher-Yates over rows: draws d = j*M + i1 are whole blocks j*M/4 ...
+  if constexpr (M > 64) {
+    // rows 0..127 as two 64-bit halves
+    uint64_t lo = 0, hi = 0;
+    if (j > 0) {
+      lo = (M / 2 == 64) ? ~0ull : ((1ull << (M / 2)) - 1ull);
 #pragma unroll
-    for (int b = 0; b < M / 4; ++b) {
-      const U4 u = draw_block(seed, kStreamInit, 0, k, j * (M / 4) + b);
+      for (int b = 0; b < M / 4; ++b) {
+        const U4 u = draw_block(seed, kStreamInit, 0, k, j * (M / 4) + b);
 #pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        const int i1 = 4 * b + w;
-        if (i1 >= M - 1) break;
-        const uint32_t i2 = (uint32_t)i1 + bounded(u[w], (uint32_t)(M - i1));
-        const uint64_t b1 = (v >> i1) & 1ull, b2 = (v >> i2) & 1ull;
-        if (b1 != b2) v ^= (1ull << i1) | (1ull << i2);
+        for (int w = 0; w < 4; ++w) {
+          const int i1 = 4 * b + w;
+          if (i1 >= M - 1) break;
+          const uint32_t i2 = (uint32_t)i1 + bounded(u[w], (uint32_t)(M - i1));
+          const uint64_t b1 = i1 < 64 ? (lo >> i1) & 1ull : (hi >> (i1 - 64)) & 1ull;
+          const uint64_t b2 = i2 < 64 ? (lo >> i2) & 1ull : (hi >> (i2 - 64)) & 1ull;
+          if (b1 != b2) {
+            if (i1 < 64) lo ^= 1ull << i1; else hi ^= 1ull << (i1 - 64);
+            if (i2 < 64) lo ^= 1ull << i2; else hi ^= 1ull << (i2 - 64);
+          }
+        }
       }
     }
+    reinterpret_cast<uint4*>(pop)[(size_t)k * M + j] =
+        make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+  } else {
+    uint64_t v = 0;
+    if (j > 0) {
+      v = (M / 2 == 64) ? ~0ull : ((1ull << (M / 2)) - 1ull);  // rows < M/2 = -1
+      // Fisher-Yates over rows: draws d = j*M + i1 are whole blocks j*M/4 ...
+#pragma unroll
+      for (int b = 0; b < M / 4; ++b) {
+        const U4 u = draw_block(seed, kStreamInit, 0, k, j * (M / 4) + b);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const int i1 = 4 * b + w;
+          if (i1 >= M - 1) break;
+          const uint32_t i2 = (uint32_t)i1 + bounded(u[w], (uint32_t)(M - i1));
+          const uint64_t b1 = (v >> i1) & 1ull, b2 = (v >> i2) & 1ull;
+          if (b1 != b2) v ^= (1ull << i1) | (1ull << i2);
+        }
+      }
+    }
+    uint32_t* dst = pop + ((size_t)k * M + j) * W;
+    dst[0] = (uint32_t)v;
+    if (W > 1) dst[1] = (uint32_t)(v >> 32);
   }
-  uint32_t* dst = pop + ((size_t)k * M + j) * W;
-  dst[0] = (uint32_t)v;
-  if (W > 1) dst[W - 1] = (uint32_t)(v >> 32);
 }
 
 // ---------------------------------------------------------------------------
@@ -94,6 +120,20 @@ __global__ __launch_bounds__(kChildBlock) void fitness_kernel_w2(
   if (st) note_zero(st, best, 0);
 }
 
+__global__ __launch_bounds__(kChildBlock) void fitness_kernel_w4(
+    const uint32_t* __restrict__ pop, uint32_t n, uint32_t m, uint32_t kind,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ comps, RunState* st) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long best = ~0ull;
+  if (k < n) {
+    uint32_t out3[3];
+    const uint32_t key =
+        fitness_w4(pop + (size_t)k * 4 * m, m, kind, comps != nullptr, out3);
+    fitness_epilogue(k, key, out3, keys, comps, &best);
+  }
+  if (st) note_zero(st, best, 0);
+}
+
 // ga_fitness_repeat: evaluation i of the launch is individual i mod n, for
 // i < n * reps, strided over a grid sized to fill every CU.
 template <int M, uint32_t NEED>
@@ -122,6 +162,20 @@ __global__ __launch_bounds__(kBlock) void fitness_repeat_w2_kernel(
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += stride) {
     keys[k] = fitness_w2(pop + (size_t)k * 2 * m, m, kind, false, nullptr);
+    k += step;
+    k = k >= n ? k - n : k;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void fitness_repeat_w4_kernel(
+    const uint32_t* __restrict__ pop, uint32_t n, uint32_t m, uint64_t total,
+    uint32_t kind, uint32_t* __restrict__ keys) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint32_t k = (uint32_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) % n);
+  const uint32_t step = (uint32_t)(stride % n);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += stride) {
+    keys[k] = fitness_w4(pop + (size_t)k * 4 * m, m, kind, false, nullptr);
     k += step;
     k = k >= n ? k - n : k;
   }
@@ -190,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void check_kernel(const uint32_t* pop,
                                                        uint32_t* bad) {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  const uint32_t W = (m + 31) / 32;
+  const uint32_t W = col_words(m);
   const uint32_t* Q = pop + (size_t)k * m * W;
   bool ok = true;
   for (uint32_t w = 0; w < W; ++w) ok &= Q[w] == 0;
@@ -229,6 +283,22 @@ __global__ __launch_bounds__(kBlock) void check_kernel(const uint32_t* pop,
     case 56: { constexpr int MM = 56; EXPR; } break; \
     case 60: { constexpr int MM = 60; EXPR; } break; \
     case 64: { constexpr int MM = 64; EXPR; } break; \
+    case 68: { constexpr int MM = 68; EXPR; } break; \
+    case 72: { constexpr int MM = 72; EXPR; } break; \
+    case 76: { constexpr int MM = 76; EXPR; } break; \
+    case 80: { constexpr int MM = 80; EXPR; } break; \
+    case 84: { constexpr int MM = 84; EXPR; } break; \
+    case 88: { constexpr int MM = 88; EXPR; } break; \
+    case 92: { constexpr int MM = 92; EXPR; } break; \
+    case 96: { constexpr int MM = 96; EXPR; } break; \
+    case 100: { constexpr int MM = 100; EXPR; } break; \
+    case 104: { constexpr int MM = 104; EXPR; } break; \
+    case 108: { constexpr int MM = 108; EXPR; } break; \
+    case 112: { constexpr int MM = 112; EXPR; } break; \
+    case 116: { constexpr int MM = 116; EXPR; } break; \
+    case 120: { constexpr int MM = 120; EXPR; } break; \
+    case 124: { constexpr int MM = 124; EXPR; } break; \
+    case 128: { constexpr int MM = 128; EXPR; } break; \
     default: return hipErrorInvalidValue;       \
   }
 
@@ -244,6 +314,11 @@ hipError_t launch_fitness(const ga_config* c, const uint32_t* pop,
                           uint32_t* keys, uint32_t* comps, RunState* st,
                           hipStream_t s) {
   const uint32_t grid = cdiv(c->n, kChildBlock);
+  if (c->m > 64) {
+    hipLaunchKernelGGL(fitness_kernel_w4, dim3(grid), dim3(kChildBlock), 0, s, pop,
+                       c->n, c->m, c->fitness, keys, comps, st);
+    return hipGetLastError();
+  }
   if (c->m > 32) {
     hipLaunchKernelGGL(fitness_kernel_w2, dim3(grid), dim3(kChildBlock), 0, s, pop,
                        c->n, c->m, c->fitness, keys, comps, st);
@@ -269,6 +344,11 @@ hipError_t launch_fitness_repeat(const ga_config* c, const uint32_t* pop,
   const uint64_t total = (uint64_t)c->n * reps;
   // eight workgroups of four waves per CU, fewer if the work is smaller
   const uint64_t grid = std::min<uint64_t>((uint64_t)cus * 8, cdiv(total, kBlock));
+  if (c->m > 64) {
+    hipLaunchKernelGGL(fitness_repeat_w4_kernel, dim3((uint32_t)grid), dim3(kBlock), 0, s,
+                       pop, c->n, c->m, total, c->fitness, keys);
+    return hipGetLastError();
+  }
   if (c->m > 32) {
     hipLaunchKernelGGL(fitness_repeat_w2_kernel, dim3((uint32_t)grid), dim3(kBlock), 0, s,
                        pop, c->n, c->m, total, c->fitness, keys);

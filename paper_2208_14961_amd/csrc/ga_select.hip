@@ -25,6 +25,7 @@ struct SelArgs {
   uint32_t* keys_b;
   SelWork* ws;
   RunState* st;
+  const uint32_t* slots;  // paper mode: slot of each rank for this launch, or null
   uint64_t seed;
   uint32_t n, count, mw, paper;
   uint32_t node, max_gen, stop_on_found;
@@ -214,6 +215,29 @@ __device__ uint32_t perm_inverse(uint64_t seed, uint32_t G, uint32_t D,
   return x;
 }
 
+// The slot pi^-1(rho) of every rank rho < D, for the generations of launches
+// 0 .. nodes-1 of a chunk (row `node` for generation gen_base + node + 1).
+// Each element is a serial cycle walk of eight-round Feistel evaluations, so
+// the whole chunk's rows are computed in one wide launch where the scatter
+// of one generation would have a single element per lane.
+__global__ __launch_bounds__(kBlock) void perm_table_kernel(const RunState* st,
+                                                            uint64_t seed, uint32_t D,
+                                                            uint32_t nodes,
+                                                            uint32_t* __restrict__ out) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (uint64_t)D * nodes) return;
+  const uint32_t node = (uint32_t)(t / D), y = (uint32_t)(t % D);
+  out[t] = perm_inverse(seed, st->gen_base + node + 1, D, y);
+}
+
+hipError_t launch_perm_table(const PopDesc& d, uint32_t count, uint32_t nodes,
+                             uint32_t* out, hipStream_t s) {
+  const uint64_t total = (uint64_t)count * nodes;
+  hipLaunchKernelGGL(perm_table_kernel, dim3(cdiv(total, kBlock)), dim3(kBlock), 0, s,
+                     d.state, d.seed, count, nodes, out);
+  return hipGetLastError();
+}
+
 // Stable compaction: the selected individuals, in index order, are copied to
 // slots rank (elitism) or pi^-1(rank) (paper mode) of the next generation.
 // The block first lists its selected (source, slot) pairs in LDS, then
@@ -273,7 +297,8 @@ __global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a, uint32_t fused)
       const bool take = less || (eq && eb < r);
       if (take && lb + min(eb, r) < a.count) {
         const uint32_t rho = lb + min(eb, r);
-        const uint32_t slot = a.paper ? perm_inverse(a.seed, G, a.count, rho) : rho;
+        const uint32_t slot =
+            a.paper ? (a.slots ? a.slots[rho] : perm_inverse(a.seed, G, a.count, rho)) : rho;
         if (slot < a.count) {
           slots[e] = slot;
           ++mine;
@@ -320,8 +345,9 @@ __global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a, uint32_t fused)
 }
 
 hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
-                         uint32_t node, hipStream_t s) {
+                         uint32_t node, const uint32_t* slots, hipStream_t s) {
   SelArgs a;
+  a.slots = slots;
   a.pop_a = d.pop_a;
   a.pop_b = d.pop_b;
   a.keys_a = d.keys_a;
@@ -331,7 +357,7 @@ hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
   a.seed = d.seed;
   a.n = d.n;
   a.count = count;
-  a.mw = d.m * ((d.m + 31) / 32);
+  a.mw = d.m * col_words(d.m);
   a.paper = d.paper;
   a.node = node;
   a.max_gen = d.max_gen;

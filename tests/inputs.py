@@ -5,14 +5,15 @@ matrices with the structure the method assumes (column 0 all +1, every
 other column balanced) and converts between the two storage layouts:
 
 * unpacked: int8 [n][m][m], entry [k, i, j] = row i, column j of matrix k;
-* packed:   uint32 [n][m][W], W = ceil(m / 32); bit (r % 32) of word r // 32
-  of column j is 1 iff entry (r, j) is -1; unused high bits are 0.
+* packed:   uint32 [n][m][W], W = 1 up to order 32, 2 up to 64, 4 up to 128;
+  bit (r % 32) of word r // 32 of column j is 1 iff entry (r, j) is -1;
+  unused bits and words are 0.
 """
 import numpy as np
 
 
 def words(m: int) -> int:
-    return (m + 31) // 32
+    return 1 if m <= 32 else (2 if m <= 64 else 4)
 
 
 def random_population(m: int, n: int, seed: int) -> np.ndarray:

@@ -30,17 +30,27 @@ def test_population_words():
     assert ga.ga_population_words(ga.Config(m=20, n=40000)) == 40000 * 20
     assert ga.ga_population_words(ga.Config(m=36, n=10)) == 10 * 36 * 2
     assert ga.ga_population_words(ga.Config(m=64, n=3)) == 3 * 64 * 2
+    assert ga.ga_population_words(ga.Config(m=68, n=3)) == 3 * 68 * 4
+    assert ga.ga_population_words(ga.Config(m=100, n=40000)) == 40000 * 100 * 4
+    assert ga.ga_population_words(ga.Config(m=128, n=5)) == 5 * 128 * 4
     assert ga.ga_population_words(ga.Config(m=6, n=3)) == 0
+    assert ga.ga_population_words(ga.Config(m=132, n=3)) == 0
 
 
 @pytest.mark.parametrize("kw", [
-    dict(m=6), dict(m=0), dict(m=68), dict(n=1), dict(n=(1 << 24) + 1), dict(fitness=6),
+    dict(m=6), dict(m=0), dict(m=132), dict(n=1), dict(n=(1 << 24) + 1), dict(fitness=6),
     dict(selection=2), dict(tournament_k=0), dict(tournament_k=65), dict(elite=10),
     dict(xo_threshold=(1 << 32) + 1), dict(mut_threshold=(1 << 32) + 1), dict(nc=0),
     dict(nr=0), dict(nc=65), dict(flags=2), dict(selection=ga.SEL_PAPER, n=10),
     dict(selection=ga.SEL_PAPER, n=12, elite=1),
     dict(flags=ga.lanes_flag(3)), dict(flags=ga.lanes_flag(1)), dict(flags=ga.lanes_flag(16)),
-    dict(m=36, flags=ga.lanes_flag(2)),
+    dict(m=36, flags=ga.lanes_flag(2)), dict(m=68, flags=ga.lanes_flag(4)),
+    dict(m=128, flags=ga.lanes_flag(2)), dict(m=64, flags=ga.lanes_flag(16)),
+    dict(m=128, flags=ga.lanes_flag(32)),
+    # keys that elitism and paper selection cannot rank (the SQ keys reach
+    # C(m-1, 2) m^2 >= 2^24 from order 80 on)
+    dict(m=80, n=100, elite=1), dict(m=80, n=100, elite=1, fitness=ga.FIT_SQ_PLUS_NNZ),
+    dict(m=128, n=400, selection=ga.SEL_PAPER, fitness=ga.FIT_SQ),
 ])
 def test_invalid_configs(kw):
     base = dict(m=8, n=10)
@@ -58,7 +68,15 @@ def test_valid_configs():
                 ga.Config(m=8, n=10, mut_threshold=0, nc=0, nr=0),
                 ga.Config(m=8, n=10, flags=ga.lanes_flag(2)),
                 ga.Config(m=32, n=10, flags=ga.STOP_ON_FOUND | ga.lanes_flag(8)),
-                ga.Config(m=64, n=10, flags=ga.lanes_flag(4))]:
+                ga.Config(m=64, n=10, flags=ga.lanes_flag(4)),
+                ga.Config(m=68, n=10, flags=ga.lanes_flag(16)),
+                ga.Config(m=128, n=10, flags=ga.lanes_flag(8)),
+                ga.Config(m=128, n=10),  # tournaments take every kind
+                ga.Config(m=76, n=100, elite=1), ga.Config(m=76, n=100, elite=1,
+                                                          fitness=ga.FIT_SQ_PLUS_NNZ),
+                ga.Config(m=128, n=100, elite=1, fitness=ga.FIT_ABS),
+                ga.Config(m=100, n=40000, selection=ga.SEL_PAPER, fitness=ga.FIT_F1,
+                          xo_threshold=1 << 32, mut_threshold=1 << 32, nc=4, nr=2)]:
         assert ga.ga_validate(cfg), cfg
 
 
@@ -93,11 +111,11 @@ def test_tuning_table_is_well_formed():
     nums = [int(x) for x in limits[:-1]]
     assert nums == sorted(nums) and len(set(nums)) == len(nums)
     rows = re.findall(r"^\s*\{([0-9, ]+)\},\s*// m = (\d+)", text, re.M)
-    assert [int(m) for _, m in rows] == list(range(4, 65, 4))
+    assert [int(m) for _, m in rows] == list(range(4, ga.MAX_ORDER + 1, 4))
     for cells, m in rows:
         lanes = [int(x) for x in cells.split(",")]
         assert len(lanes) == sizes
-        allowed = {2, 4, 8} if int(m) <= 32 else {4, 8}
+        allowed = {2, 4, 8} if int(m) <= 32 else ({4, 8} if int(m) <= 64 else {8, 16})
         assert set(lanes) <= allowed, (m, lanes)
 
 
@@ -106,4 +124,6 @@ def test_tuned_lanes_query():
     assert ga.ga_tuned_lanes(ga.Config(m=8, n=100, flags=ga.lanes_flag(2))) == 2
     assert ga.ga_tuned_lanes(ga.Config(m=20, n=40000)) in (2, 4, 8)
     assert ga.ga_tuned_lanes(ga.Config(m=64, n=50000)) in (4, 8)
+    assert ga.ga_tuned_lanes(ga.Config(m=100, n=40000)) in (8, 16)
+    assert ga.ga_tuned_lanes(ga.Config(m=128, n=40000, flags=ga.lanes_flag(8))) == 8
     assert ga.ga_tuned_lanes(ga.Config(m=6, n=100)) == 0

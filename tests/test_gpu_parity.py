@@ -12,7 +12,12 @@ from tests.gpu_util import (announce, dev_pop_from_int8, empty_keys, empty_pop,
 
 pytestmark = pytest.mark.gpu
 
-ORDERS = list(range(4, 65, 4))
+ORDERS = list(range(4, ga.MAX_ORDER + 1, 4))
+WIDE_SQ = (ga.FIT_SQ, ga.FIT_SQ_PLUS_NNZ)  # keys elitism cannot rank from order 80 on
+
+
+def lanes_of(m):
+    return (2, 4, 8) if m <= 32 else ((4, 8) if m <= 64 else (8, 16))
 KINDS = [ga.FIT_SQ, ga.FIT_ABS, ga.FIT_NNZ, ga.FIT_SQ_PLUS_NNZ, ga.FIT_F1, ga.FIT_F2]
 
 
@@ -96,7 +101,7 @@ def test_fitness_known_hadamard_and_census():
     assert dict(zip(vals.tolist(), counts.tolist())) == {0: 48, 16: 144, 48: 24}
 
 
-@pytest.mark.parametrize("m", [8, 20, 32, 36, 64])
+@pytest.mark.parametrize("m", [8, 20, 32, 36, 64, 68, 100, 128])
 def test_fitness_all_equal_columns(m):
     torch_cuda()
     announce("all-equal", m)
@@ -164,7 +169,7 @@ def test_step_tournament(m):
     _step_chain(cfg, 3)
 
 
-LANES = [(m, L) for m in ORDERS for L in ((2, 4, 8) if m <= 32 else (4, 8))]
+LANES = [(m, L) for m in ORDERS for L in lanes_of(m)]
 
 
 @pytest.mark.parametrize("m,lanes", LANES)
@@ -174,8 +179,9 @@ def test_step_lanes(m, lanes):
     torch_cuda()
     n = 2 * 128 + 45
     announce("step lanes", m, lanes, n)
-    cfg = ga.Config(m=m, n=n, seed=500 + m + lanes, elite=m % 3,
-                    fitness=KINDS[(m // 4 + lanes) % len(KINDS)],
+    kind = KINDS[(m // 4 + lanes) % len(KINDS)]
+    cfg = ga.Config(m=m, n=n, seed=500 + m + lanes,
+                    elite=0 if (m >= 80 and kind in WIDE_SQ) else m % 3, fitness=kind,
                     mut_threshold=ga.rate_threshold(1, 2), nc=1 + lanes % 3, nr=1 + m % 2,
                     flags=ga.lanes_flag(lanes))
     _step_chain(cfg, 2)
@@ -189,6 +195,10 @@ def test_step_lanes(m, lanes):
     (32, 3000, 2, 30, ga.FIT_SQ_PLUS_NNZ),
     (44, 513, 4, 100, ga.FIT_F1),
     (64, 300, 2, 3, ga.FIT_F2),
+    (68, 301, 2, 4, ga.FIT_SQ_PLUS_NNZ),
+    (100, 333, 2, 5, ga.FIT_F1),
+    (128, 257, 3, 0, ga.FIT_SQ),
+    (124, 190, 2, 9, ga.FIT_NNZ),
 ])
 def test_step_variants(m, n, t, elite, kind):
     torch_cuda()
@@ -231,6 +241,7 @@ def test_step_elite_with_ties():
 @pytest.mark.parametrize("m,N,nc,nr,kind", [
     (12, 250, 1, 2, ga.FIT_F2), (20, 100, 4, 2, ga.FIT_F1), (16, 1, 2, 2, ga.FIT_F2),
     (40, 64, 2, 8, ga.FIT_F2), (8, 4096, 3, 2, ga.FIT_F2),
+    (100, 250, 4, 2, ga.FIT_F2), (128, 33, 1, 1, ga.FIT_F1), (76, 40, 3, 5, ga.FIT_SQ),
 ])
 def test_step_paper_mode(m, N, nc, nr, kind):
     torch_cuda()
@@ -280,6 +291,11 @@ def test_run_plain_m8_config():
               xo_threshold=1 << 32, mut_threshold=1 << 32, nc=1, nr=2, max_generations=300),
     ga.Config(m=36, n=300, seed=9, max_generations=6, flags=0),
     ga.Config(m=8, n=100, seed=0, max_generations=0),
+    ga.Config(m=100, n=1000, seed=9100, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
+              xo_threshold=1 << 32, mut_threshold=1 << 32, nc=4, nr=2, max_generations=12,
+              flags=0),
+    ga.Config(m=128, n=300, seed=12, max_generations=8, flags=0),
+    ga.Config(m=84, n=500, seed=13, elite=10, fitness=ga.FIT_ABS, max_generations=10),
 ])
 def test_run_parity(cfg):
     torch_cuda()
@@ -328,6 +344,7 @@ def _mixed_configs():
         out.append(ga.Config(m=m, n=n, seed=4_000_000 + i, max_generations=int(rng.integers(5, 40)),
                              fitness=int(rng.choice([ga.FIT_SQ, ga.FIT_ABS, ga.FIT_NNZ]))))
     out.append(ga.Config(m=8, n=256, seed=1, max_generations=100))  # solves early
+    out.append(ga.Config(m=96, n=300, seed=4_000_100, max_generations=6, fitness=ga.FIT_ABS))
     return out
 
 
@@ -345,7 +362,7 @@ def test_run_batch_equals_single_runs():
 
 @pytest.mark.parametrize("lanes", ["tuned", "fewest", "most"])
 def test_run_batch_every_order(lanes):
-    """One run of every order 4..64 in one batched launch sequence: each
+    """One run of every order 4..128 in one batched launch sequence: each
     order has its own batched children kernel, with the tuned, the fewest
     or the most lanes per child."""
     torch_cuda()
@@ -354,7 +371,7 @@ def test_run_batch_every_order(lanes):
     def flags(m):
         if lanes == "tuned":
             return 0
-        return ga.lanes_flag((2 if m <= 32 else 4) if lanes == "fewest" else 8)
+        return ga.lanes_flag(lanes_of(m)[0] if lanes == "fewest" else lanes_of(m)[-1])
     cfgs = [ga.Config(m=m, n=200 + 37 * i, seed=7_000_000 + m, fitness=kinds[i % 6],
                       max_generations=4 + i % 5, flags=flags(m), nc=1 + i % 2, nr=1 + i % 3)
             for i, m in enumerate(ORDERS)]
