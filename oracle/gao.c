@@ -79,6 +79,7 @@ int gao_validate(const gao_config* c) {
     return -1;
   if (c->nc > 64 || c->nr > 64) return -1;
   if (c->mut_threshold > 0 && (c->nc == 0 || c->nr == 0)) return -1;
+  if (c->mut_shared > 1) return -1;
   if (c->selection == GAO_SEL_TOURNAMENT) {
     if (c->tournament_k < 1 || c->tournament_k > 64) return -1;
     if (c->elite >= c->n) return -1;
@@ -319,7 +320,9 @@ static void make_pair(const gao_config* c, uint32_t G, uint32_t p,
     if (dst[ch] >= c->n) continue;
     if (bern(gao_draw(c->seed, GAO_STREAM_XOVER, G, p, 2 + ch),
              c->mut_threshold)) {
-      uint32_t q = 2 * p + ch;
+      /* the child's own draws, or the generation's shared ones (first
+       * mutation method, Sec. 3.5) */
+      uint32_t q = c->mut_shared ? GAO_SHARED_MUTATION : 2 * p + ch;
       uint32_t cols[64], r1[64], r2[64];
       for (uint32_t jc = 0; jc < c->nc; ++jc)
         cols[jc] = 1 + gao_bounded(

@@ -83,7 +83,15 @@ typedef struct {
   uint32_t nr;              /* row pairs per mutated child                  */
   uint32_t max_generations; /* generation budget                            */
   uint32_t stop_on_found;   /* stop as soon as some key is 0                */
+  uint32_t mut_shared;      /* 1: the first mutation method of Sec. 3.5:
+                               every mutated child of a generation takes
+                               the same columns and row pairs, drawn once
+                               per generation (index GAO_SHARED_MUTATION) */
 } gao_config;
+
+/* the draw index of the per-generation mutation of mut_shared (above every
+ * child index) */
+#define GAO_SHARED_MUTATION 0xFFFFFFFFu
 
 typedef struct {
   int32_t found;        /* 1 if a key of 0 was reached                     */

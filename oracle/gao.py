@@ -54,6 +54,7 @@ class _Config(ctypes.Structure):
         ("nr", ctypes.c_uint32),
         ("max_generations", ctypes.c_uint32),
         ("stop_on_found", ctypes.c_uint32),
+        ("mut_shared", ctypes.c_uint32),
     ]
 
 
@@ -86,12 +87,14 @@ class Config:
     nr: int = 1
     max_generations: int = 100
     stop_on_found: bool = True
+    mut_shared: bool = False  # first mutation method of Sec. 3.5
 
     def c(self) -> _Config:
         return _Config(self.m, self.n, self.seed, self.fitness, self.selection,
                        self.tournament_k, self.elite, self.xo_threshold,
                        self.mut_threshold, self.nc, self.nr,
-                       self.max_generations, int(bool(self.stop_on_found)))
+                       self.max_generations, int(bool(self.stop_on_found)),
+                       int(bool(self.mut_shared)))
 
 
 _lib = None

@@ -388,6 +388,51 @@ def test_run_equals_repeated_steps():
     assert np.array_equal(p, pop) and np.array_equal(k, keys)
 
 
+@pytest.mark.parametrize("m,N,seed", [(12, 30, 5), (20, 16, 6), (68, 8, 7)])
+def test_step_shared_mutation_one_pattern_per_generation(m, N, seed):
+    """First mutation method (Sec. 3.5): every offspring of a generation is
+    mutated at the same column and row pair, and flipped only where the two
+    entries differ.  Compared with the same step without mutation (selection
+    and crossover draw from other streams, so they are unchanged), each child
+    differs in no entry or in the two entries of one +1/-1 pair, the pair is
+    the same for the whole generation, and the unchanged children hold equal
+    entries there.  Without the flag the children's pairs differ."""
+    base = dict(m=m, n=4 * N, seed=seed, selection=gao.SEL_PAPER, fitness=gao.FIT_F2,
+                xo_threshold=1 << 32, nc=1, nr=1)
+    shared = gao.Config(**base, mut_threshold=1 << 32, mut_shared=True)
+    own = gao.Config(**base, mut_threshold=1 << 32)
+    plain = gao.Config(**base, mut_threshold=0)
+    pop = gao.init_population(shared)
+    keys = gao.fitness(shared, pop)
+
+    def patterns(a, b):
+        pats, same = set(), []
+        for k in range(2 * N, 4 * N):
+            pos = [tuple(x) for x in np.argwhere(a[k] != b[k])]
+            if not pos:
+                same.append(k)
+                continue
+            assert len(pos) == 2 and pos[0][1] == pos[1][1], pos  # one column
+            (r1, c), (r2, _) = pos
+            assert b[k][r1, c] == -b[k][r2, c]                   # a +1/-1 pair
+            pats.add((r1, r2, c))
+        return pats, same
+
+    for g in range(3):
+        a, ka = gao.step(shared, pop, keys, g)
+        b, _ = gao.step(plain, pop, keys, g)
+        assert np.array_equal(a[:2 * N], b[:2 * N])   # parents untouched
+        pats, same = patterns(a, b)
+        assert len(pats) == 1, pats
+        (r1, r2, c), = pats
+        for k in same:
+            assert b[k][r1, c] == b[k][r2, c]
+        assert np.array_equal(gao.fitness(shared, a), ka)
+        o, _ = gao.step(own, pop, keys, g)
+        assert len(patterns(o, b)[0]) > 1
+        pop, keys = a, ka
+
+
 def test_validate():
     ok = gao.Config(m=8, n=10)
     assert gao.validate(ok)
