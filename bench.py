@@ -14,6 +14,8 @@ m = 8, n = 1,024 plain GA over 32 seeds.
 the same 24 runs one after another.
 --workload served: a Poisson stream of search requests through the server.
 --workload pmc: a short run for hardware-counter passes (no timing).
+--workload long_runs: the paper's single runs to a first Hadamard matrix
+(Sec. 4.4) with its population sizes and mutation counts.
 --workload table2: the paper's timing table (10^4 generations of 40,000
 matrices per order and key) beside its seconds.
 --workload paper_study: the paper's mutation study (generations to the first
@@ -475,6 +477,57 @@ def bench_table2(args):
     }
 
 
+# The single runs of Sec. 4.4: order -> (N, NC, NR, iterations, seconds).
+PAPER_LONG_RUNS = {20: (1_000, 2, 8, 258_875, 517), 24: (1_000, 2, 10, 9_576_814, 19_997),
+                   28: (10_000, 1, 10, 428_082, 3_054), 32: (20_000, 1, 12, 7_472_853, 94_923)}
+
+
+def bench_long_runs(args):
+    """The paper's runs to a first Hadamard matrix (Sec. 4.4): paper mode, F2,
+    crossover and mutation on every offspring, each order with the paper's N,
+    NC and NR, stopping at the first Hadamard matrix or after
+    `--long-budget` generations; one run per seed."""
+    import numpy as np
+    import torch
+    import paper_2208_14961_amd as ga
+    orders = [int(x) for x in args.long_orders.split(",")]
+    rows = []
+    for m in orders:
+        N, nc, nr, p_it, p_s = PAPER_LONG_RUNS[m]
+        bufs = buffers(ga.Config(m=m, n=4 * N, selection=ga.SEL_PAPER))
+        for k in range(args.long_seeds):
+            cfg = ga.Config(m=m, n=4 * N, seed=10_000 * m + k, selection=ga.SEL_PAPER,
+                            fitness=ga.FIT_F2, xo_threshold=1 << 32, mut_threshold=1 << 32,
+                            nc=nc, nr=nr, max_generations=args.long_budget)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = ga.ga_run(cfg, *bufs)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t
+            if r["found"]:
+                H = r["matrix"].astype(np.int64)
+                assert (H.T @ H == m * np.eye(m, dtype=np.int64)).all()
+            rows.append({"m": m, "N": N, "nc": nc, "nr": nr, "seed": cfg.seed,
+                         "found": bool(r["found"]), "generations": r["generation"],
+                         "seconds": sec, "us_per_generation": 1e6 * sec / max(1, r["generation"]),
+                         "paper_iterations": p_it, "paper_seconds": p_s,
+                         "paper_us_per_iteration": 1e6 * p_s / p_it})
+            print(f"long run: m={m} seed {cfg.seed}: found={r['found']} after {r['generation']} "
+                  f"generations, {sec:.1f} s (paper: {p_it} iterations, {p_s} s)", file=sys.stderr,
+                  flush=True)
+    first = next((r for r in rows if r["m"] == 20 and r["found"]), None)
+    return {
+        "metric": "paper-mode time to first Hadamard matrix, Sec. 4.4 configurations",
+        "value": first["seconds"] if first else None, "unit": "s", "n_gpus": 1,
+        "steps": len(rows), "warmup": 0, "ms_per_step": None, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"paper mode, F2, orders {orders} with the paper's N, NC, NR; "
+                               f"{args.long_seeds} seed(s) each, budget {args.long_budget} "
+                               "generations"},
+        "runs": rows,
+    }
+
+
 def bench_paper_study(args):
     """The paper's mutation study (Sec. 4.3): its truncation selection with
     n = 4N (N = 1000 by default), key F2 (or F1), crossover and mutation on
@@ -527,7 +580,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="default",
-                    choices=["default", "batched", "served", "pmc", "paper_study", "table2"])
+                    choices=["default", "batched", "served", "pmc", "paper_study", "table2", "long_runs"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -535,6 +588,11 @@ def main():
                     help="table2: comma-separated orders (default: the table's five)")
     ap.add_argument("--table2-generations", type=int, default=10_000,
                     help="table2: generations per run (the table's 10^4 by default)")
+    ap.add_argument("--long-orders", default="20,28",
+                    help="long_runs: comma-separated orders among 20, 24, 28, 32")
+    ap.add_argument("--long-seeds", type=int, default=1, help="long_runs: runs per order")
+    ap.add_argument("--long-budget", type=int, default=2_000_000,
+                    help="long_runs: generation budget per run")
     ap.add_argument("--study-n", type=int, default=1000,
                     help="paper_study: N, half the parent count (n = 4N)")
     ap.add_argument("--study-fitness", default="F2", choices=["F1", "F2"],
@@ -551,7 +609,7 @@ def main():
         sys.exit(1)
     fn = {"default": bench_default, "batched": bench_batched, "served": bench_served,
           "pmc": workload_pmc, "paper_study": bench_paper_study,
-          "table2": bench_table2}
+          "table2": bench_table2, "long_runs": bench_long_runs}
     out = fn[args.workload](args)
     print(json.dumps(out), flush=True)
 

@@ -86,6 +86,11 @@ typedef enum {
 
 enum {
   GA_STOP_ON_FOUND = 1u, /* ga_run: stop at the first generation with key 0 */
+  /* The first mutation method of Sec. 3.5: every mutated child of a
+   * generation takes the same nc columns and nr row pairs, the draws of
+   * index 0xFFFFFFFF (above every child index) in stream 4; without it each
+   * child q draws its own (index q, the third method).                     */
+  GA_MUT_SHARED = 2u,
   /* Lanes per child in the children kernel (the tile shape), bits 8..12 of
    * flags: 0 lets the library's tuning table choose; 2, 4, 8 or 16 force it
    * (orders 36..64: 4 or 8; orders 68..128: 8 or 16).  Results do not
@@ -110,7 +115,8 @@ typedef struct {
   uint32_t nc;              /* mutated columns per mutated child, <= 64      */
   uint32_t nr;              /* row pairs per mutated child, <= 64            */
   uint32_t max_generations; /* generation budget of ga_run                   */
-  uint32_t flags;           /* GA_STOP_ON_FOUND | lanes << GA_LANES_SHIFT    */
+  uint32_t flags;           /* GA_STOP_ON_FOUND | GA_MUT_SHARED |
+                               lanes << GA_LANES_SHIFT                       */
 } ga_config;
 
 typedef struct {
@@ -188,7 +194,9 @@ ga_status ga_fitness_repeat(const ga_config* cfg, const uint32_t* pop,
  * jc < nc, row pairs r1 = bounded(draw(4, G, q, nc + 2 ir), m),
  * r2 = bounded(draw(4, G, q, nc + 2 ir + 1), m), ir < nr; for each jc in
  * order, for each ir in order, the entries (r1, col) and (r2, col) are
- * negated iff they differ (Sec. 3.5, third method).
+ * negated iff they differ (Sec. 3.5, third method).  With GA_MUT_SHARED,
+ * q = 0xFFFFFFFF for every child: one set of columns and row pairs per
+ * generation (Sec. 3.5, first method, for nc = nr = 1).
  *
  * Paper mode (Sec. 3.3-3.5).  N = n / 4.  The 2N individuals with the
  * smallest (key, index), listed in index order as sel[0..2N-1], move to

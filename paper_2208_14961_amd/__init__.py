@@ -30,6 +30,7 @@ GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_EBUDGET, GA_ENOTFOUND = -1, -2, -3, -4, -5
 FIT_SQ, FIT_ABS, FIT_NNZ, FIT_SQ_PLUS_NNZ, FIT_F1, FIT_F2 = range(6)
 SEL_TOURNAMENT, SEL_PAPER = 0, 1
 STOP_ON_FOUND = 1
+MUT_SHARED = 2  # first mutation method of Sec. 3.5: one draw set per generation
 MAX_ORDER = 128  # largest order m the library accepts (GA_MAX_M)
 LANES_SHIFT = 8
 

@@ -84,7 +84,7 @@ ga_status validate(const ga_config* c) {
     set_error("nc=%u nr=%u: need 1..64 when mutation is on", c->nc, c->nr);
     return GA_EINVAL;
   }
-  if (c->flags & ~(uint32_t)(GA_STOP_ON_FOUND | GA_LANES_MASK)) {
+  if (c->flags & ~(uint32_t)(GA_STOP_ON_FOUND | GA_MUT_SHARED | GA_LANES_MASK)) {
     set_error("unknown flags 0x%x", c->flags);
     return GA_EINVAL;
   }
@@ -203,6 +203,7 @@ PopDesc make_desc(const ga_config* c, uint32_t* pa, uint32_t* pb,
   d.stop_on_found = stop_on_found;
   d.block_begin = 0;
   d.lanes_forced = forced_lanes(c) ? 1u : 0u;
+  d.mut_shared = (c->flags & GA_MUT_SHARED) ? 1u : 0u;
   d.lanes = forced_lanes(c) ? forced_lanes(c) : tuned_lanes(c->m, d.nchild);
   const uint32_t per_block = children_per_block(d.lanes);
   d.nblocks = (d.nchild + per_block - 1) / per_block;

@@ -360,7 +360,8 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d,
   const bool valid = 2 * pw + c < d.nchild;
 
   const uint32_t stream = u == 0 ? kStreamSelect : (u == 1 ? kStreamXover : kStreamMutate);
-  const U4 blk = draw_block(d.seed, stream, G, u < 2 ? p : 2 * p + (u - 2), 0);
+  const uint32_t mq = d.mut_shared ? kSharedMutation : 2 * p + (u - 2);
+  const U4 blk = draw_block(d.seed, stream, G, u < 2 ? p : mq, 0);
   const U4 sel = quad_bcast<0>(blk);
   const U4 xo = quad_bcast<1>(blk);
   const U4 mb0 = quad_bcast<2>(blk), mb1 = quad_bcast<3>(blk);
@@ -401,7 +402,7 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d,
     }
   }
   if ((uint64_t)(c ? xo.w : xo.z) < d.mut_thr) {
-    DrawSeq ds(d.seed, kStreamMutate, G, q, c ? mb1 : mb0);
+    DrawSeq ds(d.seed, kStreamMutate, G, d.mut_shared ? kSharedMutation : q, c ? mb1 : mb0);
     mutate_parts<M, L_>(f, l, ds, d.nc, d.nr);
   }
   uint32_t* me = lds + (g * 2 + c) * MW;

@@ -26,6 +26,10 @@ enum : uint32_t {
   kStreamPerm = 5
 };
 
+// Draw index of the mutation shared by a whole generation (GA_MUT_SHARED),
+// above every child index.
+constexpr uint32_t kSharedMutation = 0xFFFFFFFFu;
+
 // Fitness kinds (same numbering as the public header).
 enum : uint32_t {
   kFitSQ = 0,

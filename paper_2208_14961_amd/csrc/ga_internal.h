@@ -67,6 +67,7 @@ struct PopDesc {
   uint32_t nblocks;      // blocks of this population
   uint32_t lanes;        // lanes per child in the children kernel
   uint32_t lanes_forced; // 1: lanes come from the config, not the table
+  uint32_t mut_shared;   // 1: one mutation draw set per generation (Sec. 3.5, first method)
 };
 
 // Workspace of the selection pipeline of one population.

@@ -21,7 +21,8 @@ def to_oracle(cfg: ga.Config) -> gao.Config:
                       elite=cfg.elite, xo_threshold=cfg.xo_threshold,
                       mut_threshold=cfg.mut_threshold, nc=cfg.nc, nr=cfg.nr,
                       max_generations=cfg.max_generations,
-                      stop_on_found=bool(cfg.flags & ga.STOP_ON_FOUND))
+                      stop_on_found=bool(cfg.flags & ga.STOP_ON_FOUND),
+                      mut_shared=bool(cfg.flags & ga.MUT_SHARED))
 
 
 def dev_pop_from_int8(pop: np.ndarray):

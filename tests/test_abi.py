@@ -41,7 +41,7 @@ def test_population_words():
     dict(m=6), dict(m=0), dict(m=132), dict(n=1), dict(n=(1 << 24) + 1), dict(fitness=6),
     dict(selection=2), dict(tournament_k=0), dict(tournament_k=65), dict(elite=10),
     dict(xo_threshold=(1 << 32) + 1), dict(mut_threshold=(1 << 32) + 1), dict(nc=0),
-    dict(nr=0), dict(nc=65), dict(flags=2), dict(selection=ga.SEL_PAPER, n=10),
+    dict(nr=0), dict(nc=65), dict(flags=4), dict(selection=ga.SEL_PAPER, n=10),
     dict(selection=ga.SEL_PAPER, n=12, elite=1),
     dict(flags=ga.lanes_flag(3)), dict(flags=ga.lanes_flag(1)), dict(flags=ga.lanes_flag(16)),
     dict(m=36, flags=ga.lanes_flag(2)), dict(m=68, flags=ga.lanes_flag(4)),
@@ -69,6 +69,7 @@ def test_valid_configs():
                 ga.Config(m=8, n=10, flags=ga.lanes_flag(2)),
                 ga.Config(m=32, n=10, flags=ga.STOP_ON_FOUND | ga.lanes_flag(8)),
                 ga.Config(m=64, n=10, flags=ga.lanes_flag(4)),
+                ga.Config(m=12, n=40, flags=ga.MUT_SHARED | ga.STOP_ON_FOUND),
                 ga.Config(m=68, n=10, flags=ga.lanes_flag(16)),
                 ga.Config(m=128, n=10, flags=ga.lanes_flag(8)),
                 ga.Config(m=128, n=10),  # tournaments take every kind

@@ -254,6 +254,24 @@ def test_step_paper_mode(m, N, nc, nr, kind):
 # --------------------------------------------------------------------------
 # Whole runs
 # --------------------------------------------------------------------------
+@pytest.mark.parametrize("m,lanes,paper", [(12, 4, True), (20, 2, False), (44, 8, True),
+                                           (64, 4, False), (100, 16, True), (128, 8, False)])
+def test_step_shared_mutation(m, lanes, paper):
+    """The first mutation method (one draw set per generation, shared by
+    every mutated child) in every column width and tile shape family."""
+    torch_cuda()
+    announce("step shared mutation", m, lanes, paper)
+    if paper:
+        cfg = ga.Config(m=m, n=4 * 61, seed=40 + m, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
+                        xo_threshold=1 << 32, mut_threshold=1 << 32, nc=1, nr=1,
+                        flags=ga.MUT_SHARED | ga.lanes_flag(lanes))
+    else:
+        cfg = ga.Config(m=m, n=2 * 128 + 45, seed=41 + m, elite=3, fitness=ga.FIT_ABS,
+                        mut_threshold=ga.rate_threshold(1, 2), nc=2, nr=3,
+                        flags=ga.MUT_SHARED | ga.lanes_flag(lanes))
+    _step_chain(cfg, 3)
+
+
 def _run_gpu(cfg: ga.Config):
     pa, pb = empty_pop(cfg), empty_pop(cfg)
     ka, kb = empty_keys(cfg), empty_keys(cfg)
@@ -296,6 +314,9 @@ def test_run_plain_m8_config():
               flags=0),
     ga.Config(m=128, n=300, seed=12, max_generations=8, flags=0),
     ga.Config(m=84, n=500, seed=13, elite=10, fitness=ga.FIT_ABS, max_generations=10),
+    ga.Config(m=12, n=400, seed=14, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
+              xo_threshold=1 << 32, mut_threshold=1 << 32, nc=1, nr=1, max_generations=300,
+              flags=ga.STOP_ON_FOUND | ga.MUT_SHARED),
 ])
 def test_run_parity(cfg):
     torch_cuda()
