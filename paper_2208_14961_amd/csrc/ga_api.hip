@@ -43,19 +43,7 @@ ga_status hip_status(hipError_t e, const char* what) {
 
 uint32_t words_per_col(uint32_t m) { return col_words(m); }
 
-// The largest key of a kind at order m (all columns equal: every pair has
-// |c_i . c_j| = m).
-static uint64_t max_key(uint32_t m, uint32_t kind) {
-  const uint64_t P = (uint64_t)(m - 1) * (m - 2) / 2, mm = m;
-  switch (kind) {
-    case GA_FIT_SQ: return P * mm * mm;
-    case GA_FIT_ABS: return P * mm;
-    case GA_FIT_NNZ: return P;
-    case GA_FIT_SQ_PLUS_NNZ: return P * mm * mm + P;
-    case GA_FIT_F1: return 2 * P * mm;
-    default: return 2 * P;
-  }
-}
+
 
 ga_status validate(const ga_config* c) {
   if (!c) {

@@ -14,6 +14,20 @@ __host__ __device__ constexpr uint32_t col_words(uint32_t m) {
   return m <= 32 ? 1u : (m <= 64 ? 2u : 4u);
 }
 
+// The largest key of a fitness kind at order m (all columns equal: every
+// pair has |c_i . c_j| = m).
+inline uint64_t max_key(uint32_t m, uint32_t kind) {
+  const uint64_t P = (uint64_t)(m - 1) * (m - 2) / 2, mm = m;
+  switch (kind) {
+    case GA_FIT_SQ: return P * mm * mm;
+    case GA_FIT_ABS: return P * mm;
+    case GA_FIT_NNZ: return P;
+    case GA_FIT_SQ_PLUS_NNZ: return P * mm * mm + P;
+    case GA_FIT_F1: return 2 * P * mm;
+    default: return 2 * P;
+  }
+}
+
 constexpr uint32_t kMaxN = 1u << 24;        // population size limit
 constexpr uint32_t kMaxElite = 1u << 16;    // elite count limit
 constexpr uint32_t kKeyBits = 24;           // selection ranks keys < 2^24

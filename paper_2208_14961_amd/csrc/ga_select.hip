@@ -29,6 +29,7 @@ struct SelArgs {
   uint64_t seed;
   uint32_t n, count, mw, paper;
   uint32_t node, max_gen, stop_on_found;
+  uint32_t one_level;  // every key < 4096: the high digit is 0, no first pass
 };
 
 // Generation G produced by this launch and whether it runs (see RunState);
@@ -87,13 +88,22 @@ __global__ __launch_bounds__(kBlock) void sel_hist_hi(SelArgs a) {
 
 // Pass 2: every block finds the bucket (high bits) of the count-th key from
 // h1, then histograms the low 12 bits of the keys in that bucket into h2.
+// When every key of the kind is below 4096 (one_level) the bucket is 0 and
+// pass 1 is not launched.
 __global__ __launch_bounds__(kBlock) void sel_hist_lo(SelArgs a) {
   uint32_t G;
   if (!sel_generation(a, &G)) return;
   const uint32_t g = G - 1;
   const uint32_t* keys = (g & 1u) ? a.keys_b : a.keys_a;
   __shared__ uint32_t s_bucket, s_below;
-  scan_find(a.ws->h1, a.count, false, &s_bucket, &s_below);
+  if (a.one_level) {
+    if (threadIdx.x == 0) {
+      s_bucket = 0;
+      s_below = 0;
+    }
+  } else {
+    scan_find(a.ws->h1, a.count, false, &s_bucket, &s_below);
+  }
   __shared__ uint32_t h[4096];
   for (int i = threadIdx.x; i < 4096; i += kBlock) h[i] = 0;
   __syncthreads();
@@ -362,12 +372,13 @@ hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
   a.node = node;
   a.max_gen = d.max_gen;
   a.stop_on_found = d.stop_on_found;
+  a.one_level = max_key(d.m, d.kind) < 4096 ? 1u : 0u;
   const uint32_t gh = std::min<uint32_t>(cdiv(d.n, kSelTile), 1024);
   const uint32_t gt = cdiv(d.n, kSelTile);
   // up to kFusedTiles tiles, the threshold search and the tile offsets are
   // done by every block of the count and scatter launches themselves
   const uint32_t fused = gt <= kFusedTiles;
-  hipLaunchKernelGGL(sel_hist_hi, dim3(gh), dim3(kBlock), 0, s, a);
+  if (!a.one_level) hipLaunchKernelGGL(sel_hist_hi, dim3(gh), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(sel_hist_lo, dim3(gh), dim3(kBlock), 0, s, a);
   if (!fused) hipLaunchKernelGGL(sel_find, dim3(1), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(sel_count, dim3(gt), dim3(kBlock), 0, s, a, fused);
