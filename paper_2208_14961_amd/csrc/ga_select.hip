@@ -203,23 +203,34 @@ __global__ __launch_bounds__(kBlock) void sel_offsets(SelArgs a, uint32_t nb) {
 // Inverse of the keyed Feistel permutation of [0, D) (rounds run backwards,
 // cycle-walked into the domain).  For y < D the walk ends within the cycle
 // of y; the iteration bound only guarantees termination for any input.
-__device__ uint32_t perm_inverse(uint64_t seed, uint32_t G, uint32_t D,
-                                 uint32_t y) {
+__device__ __forceinline__ uint32_t feistel_half_bits(uint32_t D) {
   uint32_t h = 1;
   while ((1ull << (2 * h)) < (uint64_t)D) ++h;
+  return h;
+}
+
+// One inverse evaluation of the eight-round network on 2h bits.
+__device__ __forceinline__ uint32_t feistel_inverse(uint64_t seed, uint32_t G,
+                                                    uint32_t h, uint32_t x) {
   const uint32_t mask = (1u << h) - 1u;
+  uint32_t L = x >> h, R = x & mask;
+  for (int r = 7; r >= 0; --r) {
+    const U4 u = draw_block(seed, kStreamPerm, G, L, (uint32_t)r >> 2);
+    const uint32_t f = u[(uint32_t)r & 3u] & mask;
+    const uint32_t nl = R ^ f;
+    R = L;
+    L = nl;
+  }
+  return (L << h) | R;
+}
+
+__device__ uint32_t perm_inverse(uint64_t seed, uint32_t G, uint32_t D,
+                                 uint32_t y) {
+  const uint32_t h = feistel_half_bits(D);
   const uint64_t limit = 1ull << (2 * h);
   uint32_t x = y;
   for (uint64_t it = 0; it < limit; ++it) {
-    uint32_t L = x >> h, R = x & mask;
-    for (int r = 7; r >= 0; --r) {
-      const U4 u = draw_block(seed, kStreamPerm, G, L, (uint32_t)r >> 2);
-      const uint32_t f = u[(uint32_t)r & 3u] & mask;
-      const uint32_t nl = R ^ f;
-      R = L;
-      L = nl;
-    }
-    x = (L << h) | R;
+    x = feistel_inverse(seed, G, h, x);
     if (x < D) break;
   }
   return x;
@@ -230,20 +241,60 @@ __device__ uint32_t perm_inverse(uint64_t seed, uint32_t G, uint32_t D,
 // Each element is a serial cycle walk of eight-round Feistel evaluations, so
 // the whole chunk's rows are computed in one wide launch where the scatter
 // of one generation would have a single element per lane.
+// The walks have very uneven lengths (about 3.3 network evaluations on
+// average at 2N = 20,000, up to a dozen in a wave of 64), so each wave owns
+// a pool of kPermPerWave elements and a lane that ends a walk takes the
+// next element of the pool: the wave runs for about the pool's total walk
+// length over 64 plus one walk, not 64 times its longest walk.  Element t
+// (row t / D, rank t % D) gets exactly perm_inverse's value.
+constexpr uint32_t kPermPerWave = 512;
+
 __global__ __launch_bounds__(kBlock) void perm_table_kernel(const RunState* st,
                                                             uint64_t seed, uint32_t D,
                                                             uint32_t nodes,
                                                             uint32_t* __restrict__ out) {
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (uint64_t)D * nodes) return;
-  const uint32_t node = (uint32_t)(t / D), y = (uint32_t)(t % D);
-  out[t] = perm_inverse(seed, st->gen_base + node + 1, D, y);
+  const uint64_t total = (uint64_t)D * nodes;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t begin = wave * kPermPerWave;
+  if (begin >= total) return;  // uniform over the wave
+  const uint64_t end = min(begin + kPermPerWave, total);
+  const uint32_t gb = st->gen_base, h = feistel_half_bits(D);
+  const uint64_t limit = 1ull << (2 * h);
+  const unsigned long long below = (1ull << lane) - 1ull;  // lanes before this one
+  uint64_t next = begin + 64;  // first element not yet taken (same in every lane)
+  uint64_t e = begin + lane;   // this lane's element
+  bool busy = e < end;
+  uint32_t x = busy ? (uint32_t)(e % D) : 0u, G = busy ? gb + (uint32_t)(e / D) + 1 : 0u;
+  uint64_t it = 0;
+  while (__ballot(busy) != 0ull || next < end) {
+    if (busy) {
+      x = feistel_inverse(seed, G, h, x);
+      if (x < D || ++it == limit) {
+        out[e] = x;
+        busy = false;
+      }
+    }
+    const unsigned long long idle = __ballot(!busy);
+    if (!busy) {  // take the next element of the pool, in lane order
+      const uint64_t mine = next + (uint64_t)__popcll(idle & below);
+      if (mine < end) {
+        e = mine;
+        x = (uint32_t)(e % D);
+        G = gb + (uint32_t)(e / D) + 1;
+        it = 0;
+        busy = true;
+      }
+    }
+    next += (uint64_t)__popcll(idle);
+  }
 }
 
 hipError_t launch_perm_table(const PopDesc& d, uint32_t count, uint32_t nodes,
                              uint32_t* out, hipStream_t s) {
   const uint64_t total = (uint64_t)count * nodes;
-  hipLaunchKernelGGL(perm_table_kernel, dim3(cdiv(total, kBlock)), dim3(kBlock), 0, s,
+  const uint64_t waves = (total + kPermPerWave - 1) / kPermPerWave;
+  hipLaunchKernelGGL(perm_table_kernel, dim3(cdiv(waves * 64, kBlock)), dim3(kBlock), 0, s,
                      d.state, d.seed, count, nodes, out);
   return hipGetLastError();
 }
