@@ -238,6 +238,21 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
 ga_status ga_run_batch(const ga_config* cfgs, uint32_t count, ga_result* outs,
                        void* stream);
 
+/*
+ * Layout conversion between the paper's int8 matrices (Sec. 3.4: entry (row
+ * i, column j) of matrix k at q[k*m*m + i*m + j], values +1 and -1) and the
+ * packed layout above.  Async; one pass over each array.
+ * ga_pack: q [n][m][m] int8 (read), pop [n][m][W] (written): an entry packs
+ * as -1 iff it is negative.  bad: NULL, or a device uint32 that is
+ * increased by the number of entries other than +1 and -1.
+ * ga_unpack: pop (read), q (written) with +1 and -1.
+ * Neither checks the invariants (ga_check_invariants does).
+ */
+ga_status ga_pack(const ga_config* cfg, const int8_t* q, uint32_t* pop,
+                  uint32_t* bad, void* stream);
+ga_status ga_unpack(const ga_config* cfg, const uint32_t* pop, int8_t* q,
+                    void* stream);
+
 /* Count (on the host, synchronously) the matrices of pop breaking the
  * invariants: column 0 words not 0, a column not balanced, bits set above
  * row m - 1. */

@@ -131,6 +131,8 @@ def lib() -> ctypes.CDLL:
             "ga_run": (i32, [P(_Config), vp, vp, vp, vp, P(_Result), vp]),
             "ga_run_batch": (i32, [P(_Config), u32, P(_Result), vp]),
             "ga_check_invariants": (i32, [P(_Config), vp, P(u32), vp]),
+            "ga_pack": (i32, [P(_Config), vp, vp, vp, vp]),
+            "ga_unpack": (i32, [P(_Config), vp, vp, vp]),
             "ga_server_create": (i32, [u64, i32, P(vp)]),
             "ga_submit": (i32, [vp, P(_Config), P(u64)]),
             "ga_poll": (i32, [vp, u64, P(_Result)]),
@@ -232,6 +234,32 @@ def ga_run_batch(cfgs: Sequence[Config], stream=None) -> list:
     res = (_Result * len(cfgs))()
     _check(lib().ga_run_batch(arr, len(cfgs), res, _stream(stream)))
     return [_result(res[i], cfgs[i].m) for i in range(len(cfgs))]
+
+
+def _dev8(t, shape, name) -> ctypes.c_void_p:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.int8 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous int8 tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def ga_pack(cfg: Config, q, pop, bad=None, stream=None) -> None:
+    """int8 matrices q (n, m, m), +1/-1, into the packed population pop;
+    bad: None or an int32 device tensor of shape (1,) increased by the
+    number of entries other than +1 and -1."""
+    b = ctypes.c_void_p(None) if bad is None else _dev(bad, (1,), "bad")
+    _check(lib().ga_pack(ctypes.byref(cfg.c()), _dev8(q, (cfg.n, cfg.m, cfg.m), "q"),
+                         _dev(pop, pop_shape(cfg), "pop"), b, _stream(stream)))
+
+
+def ga_unpack(cfg: Config, pop, q, stream=None) -> None:
+    """The packed population pop as int8 matrices q (n, m, m) of +1/-1."""
+    _check(lib().ga_unpack(ctypes.byref(cfg.c()), _dev(pop, pop_shape(cfg), "pop"),
+                           _dev8(q, (cfg.n, cfg.m, cfg.m), "q"), _stream(stream)))
 
 
 def ga_check_invariants(cfg: Config, pop, stream=None) -> int:

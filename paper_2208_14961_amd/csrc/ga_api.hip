@@ -593,6 +593,30 @@ ga_status ga_timing_read(double* mean_ms, uint64_t* launches) {
   return GA_OK;
 }
 
+ga_status ga_pack(const ga_config* cfg, const int8_t* q, uint32_t* pop,
+                  uint32_t* bad, void* stream) {
+  ga_status st = validate(cfg);
+  if (st != GA_OK) return st;
+  if (!q || !pop) {
+    set_error("q or pop is NULL");
+    return GA_EINVAL;
+  }
+  GA_TRY(launch_pack(cfg, q, pop, bad, (hipStream_t)stream), "pack kernel");
+  return GA_OK;
+}
+
+ga_status ga_unpack(const ga_config* cfg, const uint32_t* pop, int8_t* q,
+                    void* stream) {
+  ga_status st = validate(cfg);
+  if (st != GA_OK) return st;
+  if (!q || !pop) {
+    set_error("q or pop is NULL");
+    return GA_EINVAL;
+  }
+  GA_TRY(launch_unpack(cfg, pop, q, (hipStream_t)stream), "unpack kernel");
+  return GA_OK;
+}
+
 ga_status ga_check_invariants(const ga_config* cfg, const uint32_t* pop,
                               uint32_t* bad_count, void* stream) {
   ga_status st = validate(cfg);

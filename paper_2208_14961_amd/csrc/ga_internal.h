@@ -135,6 +135,10 @@ hipError_t launch_reset_state(RunState* st, hipStream_t s);
 hipError_t launch_set_state(RunState* st, uint32_t gen, hipStream_t s);
 hipError_t launch_check(const ga_config* c, const uint32_t* pop,
                         uint32_t* bad, hipStream_t s);
+// int8 [n][m][m] <-> packed; bad nullable
+hipError_t launch_pack(const ga_config* c, const int8_t* q, uint32_t* pop, uint32_t* bad,
+                       hipStream_t s);
+hipError_t launch_unpack(const ga_config* c, const uint32_t* pop, int8_t* q, hipStream_t s);
 
 // ---- lanes per child (the children kernel's tile shape) -------------------
 // 2, 4 or 8 for orders up to 32 (one word per column); 4 or 8 up to 64 (two

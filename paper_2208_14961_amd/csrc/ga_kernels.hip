@@ -263,6 +263,50 @@ __global__ __launch_bounds__(kBlock) void check_kernel(const uint32_t* pop,
 }
 
 // ---------------------------------------------------------------------------
+// Layout conversion: one thread per (matrix k, column j); the threads of a
+// matrix touch consecutive bytes of each row.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kBlock) void pack_kernel(const int8_t* __restrict__ q,
+                                                      uint32_t* __restrict__ pop,
+                                                      uint32_t n, uint32_t* bad) {
+  constexpr int W = (int)col_words(M);
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (uint64_t)n * M) return;
+  const uint32_t k = (uint32_t)(t / M), j = (uint32_t)(t % M);
+  const int8_t* src = q + (size_t)k * M * M + j;
+  uint32_t w[4] = {0, 0, 0, 0};
+  uint32_t odd = 0;
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    const int8_t e = src[(size_t)r * M];
+    w[r / 32] |= (e < 0 ? 1u : 0u) << (r % 32);
+    odd += (e != 1 && e != -1) ? 1u : 0u;
+  }
+  uint32_t* dst = pop + ((size_t)k * M + j) * W;
+#pragma unroll
+  for (int i = 0; i < W; ++i) dst[i] = w[i];
+  if (odd && bad) atomicAdd(bad, odd);
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void unpack_kernel(const uint32_t* __restrict__ pop,
+                                                        int8_t* __restrict__ q, uint32_t n) {
+  constexpr int W = (int)col_words(M);
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (uint64_t)n * M) return;
+  const uint32_t k = (uint32_t)(t / M), j = (uint32_t)(t % M);
+  const uint32_t* src = pop + ((size_t)k * M + j) * W;
+  uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < W; ++i) w[i] = src[i];
+  int8_t* dst = q + (size_t)k * M * M + j;
+#pragma unroll
+  for (int r = 0; r < M; ++r)
+    dst[(size_t)r * M] = ((w[r / 32] >> (r % 32)) & 1u) ? (int8_t)-1 : (int8_t)1;
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 #define GA_DISPATCH_M(m, EXPR)                  \
@@ -307,6 +351,21 @@ hipError_t launch_init(const ga_config* c, uint32_t* pop, hipStream_t s) {
   GA_DISPATCH_M(c->m, hipLaunchKernelGGL(init_kernel<MM>, dim3(grid),
                                          dim3(kBlock), 0, s, pop, c->n,
                                          c->seed));
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const ga_config* c, const int8_t* q, uint32_t* pop, uint32_t* bad,
+                       hipStream_t s) {
+  const uint32_t grid = cdiv((uint64_t)c->n * c->m, kBlock);
+  GA_DISPATCH_M(c->m, hipLaunchKernelGGL(pack_kernel<MM>, dim3(grid), dim3(kBlock), 0, s, q,
+                                         pop, c->n, bad));
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const ga_config* c, const uint32_t* pop, int8_t* q, hipStream_t s) {
+  const uint32_t grid = cdiv((uint64_t)c->n * c->m, kBlock);
+  GA_DISPATCH_M(c->m, hipLaunchKernelGGL(unpack_kernel<MM>, dim3(grid), dim3(kBlock), 0, s,
+                                         pop, q, c->n));
   return hipGetLastError();
 }
 

@@ -119,6 +119,40 @@ def test_fitness_all_equal_columns(m):
 
 
 # --------------------------------------------------------------------------
+# Layout conversion
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m", [4, 20, 32, 36, 64, 68, 96, 100, 128])
+def test_pack_unpack(m):
+    """The paper's int8 layout to the packed one and back: the packed words
+    equal the layout's definition (computed on the host by tests/inputs),
+    the round trip is the identity, and entries other than +1/-1 are
+    counted (packing as -1 iff negative)."""
+    torch = torch_cuda()
+    n = 257
+    announce("pack", m, n)
+    pop = inputs.random_population(m, n, seed=900 + m)
+    cfg = ga.Config(m=m, n=n)
+    q = torch.from_numpy(pop).to("cuda")
+    packed = empty_pop(cfg)
+    bad = torch.zeros((1,), dtype=torch.int32, device="cuda")
+    ga.ga_pack(cfg, q, packed, bad)
+    assert np.array_equal(packed.cpu().numpy().view(np.uint32), inputs.pack(pop))
+    assert int(bad.item()) == 0 and ga.ga_check_invariants(cfg, packed) == 0
+    back = torch.zeros_like(q)
+    ga.ga_unpack(cfg, packed, back)
+    assert np.array_equal(back.cpu().numpy(), pop)
+    odd = pop.copy()
+    rng = np.random.default_rng(m)
+    at = rng.integers(0, n * m * m, 40)
+    flat = odd.reshape(-1)
+    flat[at] = rng.choice(np.array([0, 2, -3, 5, -128], dtype=np.int8), 40)
+    ga.ga_pack(cfg, torch.from_numpy(odd).to("cuda"), packed, bad)
+    assert int(bad.item()) == len(set(at.tolist()))
+    assert np.array_equal(packed.cpu().numpy().view(np.uint32),
+                          inputs.pack(np.where(odd < 0, -1, 1).astype(np.int8)))
+
+
+# --------------------------------------------------------------------------
 # Initial population
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("m", ORDERS)
