@@ -534,6 +534,19 @@ def test_full_size_m32_n200000_elite_generation():
     assert np.array_equal(int8_from_dev_pop(nxt, 32), pop)
 
 
+def test_full_size_table2_m100_n40000_run():
+    """The Table 2 configuration at its full size (m = 100, 40,000 matrices,
+    paper mode, F2, NC = 4, NR = 2, the benchmark's seed) through ga_run,
+    whose chunk computes the slot permutations in one launch: two whole
+    generations, population and keys, against the oracle."""
+    torch_cuda()
+    announce("full table2 m100 n40000")
+    cfg = ga.Config(m=100, n=40000, seed=9100, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
+                    xo_threshold=1 << 32, mut_threshold=1 << 32, nc=4, nr=2,
+                    max_generations=2, flags=0)
+    _same_run(cfg)
+
+
 def test_invalid_configs_rejected():
     torch_cuda()
     bad = ga.Config(m=18, n=100)
