@@ -68,6 +68,18 @@ def ops_per_eval(m: int, kind: int) -> int:
     return pairs * sum(pair_mix(kind, (m + 31) // 32))
 
 
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def child_bytes(m: int, t: int = 2):
+    """Algorithmic HBM bytes per child of a tournament generation: the
+    winner's packed row and the t contestants' keys read, the child's row and
+    key written (each parent row is read once per child that takes it)."""
+    w = 1 if m <= 32 else (2 if m <= 64 else 4)
+    row = m * w * 4
+    return row + 4 * t, row + 4
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -262,13 +274,34 @@ def bench_default(args):
     ga.ga_run(cfg, *bufs)
     mean_ms, launches = ga.ga_timing_read()
     ga.ga_timing_enable(False)
-    achieved = n * ops_per_eval(m, ga.FIT_SQ) / (mean_ms * 1e-3) / 1e12
-    peak = alu_peak_tops(m, ga.FIT_SQ)
+    ops = ops_per_eval(m, ga.FIT_SQ)
+    rd, wr = child_bytes(m)
+    alu_achieved = n * ops / (mean_ms * 1e-3) / 1e12
+    alu_peak = alu_peak_tops(m, ga.FIT_SQ)
+    # the roofline that bounds the kernel: its arithmetic intensity against
+    # the ridge point of the ALU mix peak over the HBM peak
+    intensity = ops / (rd + wr)
+    ridge = alu_peak * 1e12 / (HBM_PEAK_GBS * 1e9)
+    hbm_achieved = n * (rd + wr) / (mean_ms * 1e-3) / 1e9
     kernel = f"children_one_kernel<20, 1u, {ga.ga_tuned_lanes(cfg)}>"
     tr = measured_traffic()
     # the counters hold for the variant they were taken on
     traffic = (tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
                if tr is not None and tr.get("kernel") == kernel else None)
+    alu = {"achieved": alu_achieved, "peak": alu_peak, "unit": "TOP/s",
+           "frac": alu_achieved / alu_peak, "frac_of_simple_op_peak": alu_achieved / SIMPLE_OP_TOPS,
+           "ops_per_eval": ops}
+    if intensity < ridge:
+        roofline = {"bound": "hbm", "kernel": kernel, "achieved": hbm_achieved,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_achieved / HBM_PEAK_GBS,
+                    "traffic": traffic, "algorithmic_bytes_per_launch": n * (rd + wr), "alu": alu}
+    else:
+        roofline = {"bound": "alu", "kernel": kernel, **{k: alu[k] for k in
+                    ("achieved", "peak", "unit", "frac")}, "traffic": traffic,
+                    "algorithmic_bytes_per_launch": n * (rd + wr),
+                    "frac_of_simple_op_peak": alu["frac_of_simple_op_peak"], "ops_per_eval": ops}
+    roofline.update({"intensity_ops_per_byte": intensity, "ridge_ops_per_byte": ridge,
+                     "mean_generation_ms": mean_ms, "generations_timed": launches})
     out = {
         "metric": "Gram+fitness evals/s and generations/s at m=20,pop=40k; p50/p99 time-to-solve",
         "value": args.steps * evals / dt,
@@ -288,12 +321,7 @@ def bench_default(args):
         "generations_per_s": args.steps * G / dt,
         "abs_keyed": {"value": args.steps * evals / dt_abs, "unit": "evals/s",
                       "generations_per_s": args.steps * G / dt_abs},
-        "roofline": {"bound": "alu", "kernel": kernel,
-                     "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved / peak, "traffic": traffic,
-                     "frac_of_simple_op_peak": achieved / SIMPLE_OP_TOPS,
-                     "mean_generation_ms": mean_ms, "generations_timed": launches,
-                     "ops_per_eval": ops_per_eval(m, ga.FIT_SQ)},
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, n, 1, ga.FIT_SQ, budget_s=args.cpu_seconds)
