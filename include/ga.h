@@ -230,10 +230,12 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
                  void* stream);
 
 /*
- * Several independent runs advanced together, one generation of every
- * active population per launch (tournament mode only).  Synchronous.
- * cfgs, outs: host arrays of count entries.  The library allocates the
- * populations.  Every run's result equals what ga_run gives for it alone.
+ * Several independent runs advanced together: one children launch per order
+ * and generation covers every active run of that order; runs with elitism
+ * or paper mode add their own selection launches, on a workspace of their
+ * own.  Synchronous.  cfgs, outs: host arrays of count entries.  The library
+ * allocates the populations.  Every run's result equals what ga_run gives
+ * for it alone.
  */
 ga_status ga_run_batch(const ga_config* cfgs, uint32_t count, ga_result* outs,
                        void* stream);
@@ -270,7 +272,8 @@ ga_status ga_timing_enable(int on);
 ga_status ga_timing_read(double* mean_ms, uint64_t* launches);
 
 /* -------------------------------------------------------------------------
- * Search server: continuous batching of independent runs (tournament mode).
+ * Search server: continuous batching of independent runs (every selection
+ * mode, as ga_run_batch).
  * Requests are admitted while their device memory fits the HBM budget;
  * admitted populations stay resident on the device and advance one
  * generation per server tick together with every other active request; a

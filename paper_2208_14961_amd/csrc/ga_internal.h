@@ -61,6 +61,8 @@ inline bool run_done(const RunState& s, uint32_t max_gen, bool stop_on_found) {
 }
 
 // One population in a step launch.
+struct SelWork;
+
 struct PopDesc {
   uint32_t* pop_a;
   uint32_t* pop_b;
@@ -82,6 +84,8 @@ struct PopDesc {
   uint32_t lanes;        // lanes per child in the children kernel
   uint32_t lanes_forced; // 1: lanes come from the config, not the table
   uint32_t mut_shared;   // 1: one mutation draw set per generation (Sec. 3.5, first method)
+  SelWork* sel;          // batched and served runs with elitism or paper mode: their
+                         // selection workspace (null otherwise)
 };
 
 // Workspace of the selection pipeline of one population.
@@ -176,11 +180,15 @@ struct RunBuffers {
   uint32_t* pop_b = nullptr;
   uint32_t* keys_a = nullptr;
   uint32_t* keys_b = nullptr;
-  void* base = nullptr;   // single allocation holding all four
+  SelWork* sel = nullptr;  // runs with elitism or paper mode
+  void* base = nullptr;   // single allocation holding all of them
 };
 size_t run_bytes(const ga_config* c);
 ga_status alloc_run(const ga_config* c, RunBuffers* b);
 void free_run(RunBuffers* b);
+// The launch descriptor of a batched or served run (with its selection
+// workspace, if it selects).
+PopDesc run_desc(const ga_config* c, const RunBuffers& b, RunState* st);
 
 // Starts runs in place: state reset, initial population and its fitness.
 ga_status start_runs(const ga_config* cfgs, const RunBuffers* bufs,
@@ -214,6 +222,8 @@ class MultiLaunch {
     size_t cap_desc = 0, cap_map = 0;
     uint32_t ndesc = 0, nblocks = 0;
   };
+  // launch `node` for one group: its runs' selections, then its children
+  ga_status enqueue_group(const Group& g, uint32_t node, hipStream_t s);
   Group groups_[kOrders];            // one per order 4, 8, .., 128
   hipGraphExec_t graph_ = nullptr;
   uint32_t graph_gens_ = 0;

@@ -19,23 +19,37 @@ namespace ga {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Elitism and paper mode select every generation; such a run carries its
+// own selection workspace.
+static bool selects(const ga_config* c) {
+  return c->selection == GA_SEL_PAPER || c->elite > 0;
+}
+
 size_t run_bytes(const ga_config* c) {
   const size_t pop = (size_t)c->n * c->m * words_per_col(c->m) * 4;
   const size_t keys = (size_t)c->n * 4;
-  return 2 * align256(pop) + 2 * align256(keys);
+  return 2 * align256(pop) + 2 * align256(keys) + (selects(c) ? align256(sizeof(SelWork)) : 0);
 }
 
 ga_status alloc_run(const ga_config* c, RunBuffers* b) {
   const size_t pop = align256((size_t)c->n * c->m * words_per_col(c->m) * 4);
   const size_t keys = align256((size_t)c->n * 4);
   char* base = nullptr;
-  GA_TRY(hipMalloc(&base, 2 * pop + 2 * keys), "hipMalloc(run)");
+  GA_TRY(hipMalloc(&base, run_bytes(c)), "hipMalloc(run)");
   b->base = base;
   b->pop_a = reinterpret_cast<uint32_t*>(base);
   b->pop_b = reinterpret_cast<uint32_t*>(base + pop);
   b->keys_a = reinterpret_cast<uint32_t*>(base + 2 * pop);
   b->keys_b = reinterpret_cast<uint32_t*>(base + 2 * pop + keys);
+  b->sel = selects(c) ? reinterpret_cast<SelWork*>(base + 2 * pop + 2 * keys) : nullptr;
   return GA_OK;
+}
+
+PopDesc run_desc(const ga_config* c, const RunBuffers& b, RunState* st) {
+  PopDesc d = make_desc(c, b.pop_a, b.pop_b, b.keys_a, b.keys_b, st, c->max_generations,
+                        (c->flags & GA_STOP_ON_FOUND) ? 1u : 0u);
+  d.sel = b.sel;
+  return d;
 }
 
 void free_run(RunBuffers* b) {
@@ -133,11 +147,27 @@ ga_status MultiLaunch::set(const PopDesc* descs, uint32_t count,
   return GA_OK;
 }
 
+// Launch `node` of a chunk for one order group: the selections of its runs
+// that select (elitism, paper mode; each on its own workspace), then the
+// group's children launch.
+ga_status MultiLaunch::enqueue_group(const Group& g, uint32_t node, hipStream_t s) {
+  for (uint32_t i = 0; i < g.ndesc; ++i) {
+    const PopDesc& d = g.hdesc[i];
+    if (d.sel)
+      GA_TRY(launch_select(d, d.paper ? d.n / 2 : d.elite, d.sel, node, nullptr, s),
+             "selection kernels");
+  }
+  GA_TRY(launch_children(g.desc, g.map, g.nblocks, g.m, g.lanes, node, s),
+         "children kernel");
+  return GA_OK;
+}
+
 ga_status MultiLaunch::enqueue_generation(uint32_t node, hipStream_t s) {
-  for (Group& g : groups_)
-    if (g.nblocks)
-      GA_TRY(launch_children(g.desc, g.map, g.nblocks, g.m, g.lanes, node, s),
-             "children kernel");
+  for (Group& g : groups_) {
+    if (!g.nblocks) continue;
+    const ga_status st = enqueue_group(g, node, s);
+    if (st != GA_OK) return st;
+  }
   return GA_OK;
 }
 
@@ -176,9 +206,7 @@ ga_status MultiLaunch::launch_chunk(uint32_t gens, hipStream_t s) {
       if (!gr.ndesc) continue;
       hipStream_t b = branch_[gi];
       st = hip_status(hipStreamWaitEvent(b, fork_[kOrders], 0), "hipStreamWaitEvent");
-      for (uint32_t i = 0; i < gens && st == GA_OK; ++i)
-        st = hip_status(launch_children(gr.desc, gr.map, gr.nblocks, gr.m, gr.lanes, i, b),
-                        "children kernel");
+      for (uint32_t i = 0; i < gens && st == GA_OK; ++i) st = enqueue_group(gr, i, b);
       if (st == GA_OK)
         st = hip_status(launch_advance(gr.desc, gr.ndesc, gens, b),
                         "advance kernel");
@@ -203,6 +231,8 @@ ga_status MultiLaunch::launch_chunk(uint32_t gens, hipStream_t s) {
 // Starts a run in place: state reset, initial population, its fitness.
 static ga_status start_run(const ga_config* c, const RunBuffers& b,
                            RunState* st, hipStream_t s) {
+  // the selection passes expect zero histograms on entry (and leave them so)
+  if (b.sel) GA_TRY(hipMemsetAsync(b.sel, 0, sizeof(SelWork), s), "hipMemsetAsync(selection)");
   GA_TRY(launch_reset_state(st, s), "state kernel");
   GA_TRY(launch_init(c, b.pop_a, s), "init kernel");
   GA_TRY(launch_fitness(c, b.pop_a, b.keys_a, nullptr, st, s), "fitness kernel");
@@ -231,11 +261,6 @@ extern "C" ga_status ga_run_batch(const ga_config* cfgs, uint32_t count,
   for (uint32_t i = 0; i < count; ++i) {
     ga_status v = validate(&cfgs[i]);
     if (v != GA_OK) return v;
-    if (cfgs[i].selection != GA_SEL_TOURNAMENT || cfgs[i].elite != 0) {
-      set_error("ga_run_batch: run %u: batched runs use tournament selection "
-                "without elites", i);
-      return GA_EINVAL;
-    }
   }
   // The batch runs on a private stream after the caller's stream is idle
   // (the call is synchronous), so its generation chunks can be graphs.
@@ -270,10 +295,7 @@ extern "C" ga_status ga_run_batch(const ga_config* cfgs, uint32_t count,
     std::vector<PopDesc> descs(count);
     uint32_t gmax = 0;
     for (uint32_t i = 0; i < count; ++i) {
-      descs[i] = make_desc(&cfgs[i], bufs[i].pop_a, bufs[i].pop_b,
-                           bufs[i].keys_a, bufs[i].keys_b, &states[i],
-                           cfgs[i].max_generations,
-                           (cfgs[i].flags & GA_STOP_ON_FOUND) ? 1u : 0u);
+      descs[i] = run_desc(&cfgs[i], bufs[i], &states[i]);
       gmax = std::max(gmax, cfgs[i].max_generations);
     }
     rc = ml.set(descs.data(), count, s);

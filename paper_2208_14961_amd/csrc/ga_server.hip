@@ -138,10 +138,7 @@ static void worker_main(ga_server* S) {
     if (changed) {
       std::vector<PopDesc> descs;
       for (Request* r : active)
-        descs.push_back(make_desc(&r->cfg, r->buf.pop_a, r->buf.pop_b,
-                                  r->buf.keys_a, r->buf.keys_b,
-                                  &states[r->slot], r->cfg.max_generations,
-                                  (r->cfg.flags & GA_STOP_ON_FOUND) ? 1u : 0u));
+        descs.push_back(run_desc(&r->cfg, r->buf, &states[r->slot]));
       st = ml.set(descs.data(), (uint32_t)descs.size(), stream);
       if (st != GA_OK) break;
       changed = false;
@@ -161,10 +158,7 @@ static void worker_main(ga_server* S) {
         still.push_back(r);
         continue;
       }
-      const PopDesc d = make_desc(&r->cfg, r->buf.pop_a, r->buf.pop_b,
-                                  r->buf.keys_a, r->buf.keys_b,
-                                  &states[r->slot], r->cfg.max_generations,
-                                  (r->cfg.flags & GA_STOP_ON_FOUND) ? 1u : 0u);
+      const PopDesc d = run_desc(&r->cfg, r->buf, &states[r->slot]);
       ga_status rr = hip_status(launch_finish_one(d, stream), "finish kernel");
       if (rr == GA_OK)
         rr = hip_status(hipMemcpyAsync(&host[r->slot], &states[r->slot],
@@ -255,10 +249,6 @@ ga_status ga_submit(ga_server* S, const ga_config* cfg, uint64_t* request_id) {
   }
   ga_status v = validate(cfg);
   if (v != GA_OK) return v;
-  if (cfg->selection != GA_SEL_TOURNAMENT || cfg->elite != 0) {
-    set_error("served runs use tournament selection without elites");
-    return GA_EINVAL;
-  }
   const size_t bytes = run_bytes(cfg);
   if (bytes > S->budget) {
     set_error("request needs %zu bytes, the budget is %llu", bytes,

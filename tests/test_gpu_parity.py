@@ -415,6 +415,55 @@ def test_run_batch_equals_single_runs():
         assert np.array_equal(got["matrix"], opop[want["index"]])
 
 
+def _selecting_configs():
+    """Runs that select every generation (paper mode, elitism) mixed with
+    plain tournaments, three of them sharing order 12's launch."""
+    paper = dict(selection=ga.SEL_PAPER, xo_threshold=1 << 32, mut_threshold=1 << 32)
+    return [
+        ga.Config(m=12, n=400, seed=61, fitness=ga.FIT_F2, nc=1, nr=2, max_generations=40, **paper),
+        ga.Config(m=12, n=301, seed=62, max_generations=25),
+        ga.Config(m=12, n=500, seed=63, elite=9, fitness=ga.FIT_NNZ, max_generations=20, flags=0),
+        ga.Config(m=20, n=700, seed=64, elite=7, fitness=ga.FIT_SQ, max_generations=12, flags=0),
+        ga.Config(m=36, n=240, seed=65, fitness=ga.FIT_F1, nc=3, nr=2, max_generations=8, flags=0,
+                  **paper),
+        ga.Config(m=68, n=120, seed=66, fitness=ga.FIT_F2, nc=2, nr=2, max_generations=5, flags=0,
+                  **paper),
+        ga.Config(m=8, n=256, seed=67, fitness=ga.FIT_F2, nc=1, nr=1, max_generations=200,
+                  flags=ga.STOP_ON_FOUND | ga.MUT_SHARED, **paper),
+    ]
+
+
+def _equals_oracle_run(cfg, got):
+    want, opop, _ = gao.run(to_oracle(cfg))
+    for k in ("found", "generation", "index", "best_key"):
+        assert got[k] == want[k], (cfg, got, want)
+    assert np.array_equal(got["matrix"], opop[want["index"]])
+
+
+def test_run_batch_with_selection():
+    """Batched runs with paper-mode and elitist selection (each run's own
+    selection launches before its order's shared children launch) equal
+    their single runs in the oracle."""
+    torch_cuda()
+    cfgs = _selecting_configs()
+    announce("batch with selection", len(cfgs))
+    for cfg, got in zip(cfgs, ga.ga_run_batch(cfgs)):
+        _equals_oracle_run(cfg, got)
+
+
+def test_server_with_selection():
+    torch_cuda()
+    cfgs = _selecting_configs()
+    announce("server with selection", len(cfgs))
+    srv = ga.Server(hbm_budget_bytes=1 << 30)
+    try:
+        ids = [srv.submit(c) for c in cfgs]
+        for cfg, i in zip(cfgs, ids):
+            _equals_oracle_run(cfg, srv.wait(i))
+    finally:
+        srv.close()
+
+
 @pytest.mark.parametrize("lanes", ["tuned", "fewest", "most"])
 def test_run_batch_every_order(lanes):
     """One run of every order 4..128 in one batched launch sequence: each
