@@ -38,6 +38,7 @@ constexpr int kOctChildren = 8;             // children per block, orders >= 36
 constexpr int kOrders = GA_MAX_M / 4;       // orders 4, 8, .., 128
 constexpr int kSelTile = 512;               // elements per block, selection
 constexpr uint64_t kMaxPermTable = 1u << 24;  // entries of a chunk's slot table
+constexpr uint32_t kBatchTableRows = 32;      // generations per batched chunk with a table
 constexpr int kMaxSelBlocks = kMaxN / kSelTile;
 
 // Device-resident progress of one run.  Generation g of the run lives in
@@ -86,6 +87,8 @@ struct PopDesc {
   uint32_t mut_shared;   // 1: one mutation draw set per generation (Sec. 3.5, first method)
   SelWork* sel;          // batched and served runs with elitism or paper mode: their
                          // selection workspace (null otherwise)
+  uint32_t* slots;       // batched and served paper-mode runs: kBatchTableRows rows of
+                         // slot permutations for a chunk (null: walked inline)
 };
 
 // Workspace of the selection pipeline of one population.
@@ -181,6 +184,7 @@ struct RunBuffers {
   uint32_t* keys_a = nullptr;
   uint32_t* keys_b = nullptr;
   SelWork* sel = nullptr;  // runs with elitism or paper mode
+  uint32_t* slots = nullptr;  // paper-mode runs: a chunk's slot table
   void* base = nullptr;   // single allocation holding all of them
 };
 size_t run_bytes(const ga_config* c);
@@ -222,8 +226,9 @@ class MultiLaunch {
     size_t cap_desc = 0, cap_map = 0;
     uint32_t ndesc = 0, nblocks = 0;
   };
-  // launch `node` for one group: its runs' selections, then its children
-  ga_status enqueue_group(const Group& g, uint32_t node, hipStream_t s);
+  // launch `node` for one group: its runs' selections (paper mode reading
+  // row `node` of the slot tables when `tables`), then its children
+  ga_status enqueue_group(const Group& g, uint32_t node, bool tables, hipStream_t s);
   Group groups_[kOrders];            // one per order 4, 8, .., 128
   hipGraphExec_t graph_ = nullptr;
   uint32_t graph_gens_ = 0;

@@ -25,10 +25,19 @@ static bool selects(const ga_config* c) {
   return c->selection == GA_SEL_PAPER || c->elite > 0;
 }
 
+// Paper-mode runs whose chunk table stays small get one (the batched graph
+// computes a chunk's slot permutations in one launch, as ga_run does).
+static size_t table_bytes(const ga_config* c) {
+  if (c->selection != GA_SEL_PAPER) return 0;
+  const uint64_t entries = (uint64_t)(c->n / 2) * kBatchTableRows;
+  return entries <= kMaxPermTable ? align256(entries * sizeof(uint32_t)) : 0;
+}
+
 size_t run_bytes(const ga_config* c) {
   const size_t pop = (size_t)c->n * c->m * words_per_col(c->m) * 4;
   const size_t keys = (size_t)c->n * 4;
-  return 2 * align256(pop) + 2 * align256(keys) + (selects(c) ? align256(sizeof(SelWork)) : 0);
+  return 2 * align256(pop) + 2 * align256(keys) + (selects(c) ? align256(sizeof(SelWork)) : 0) +
+         table_bytes(c);
 }
 
 ga_status alloc_run(const ga_config* c, RunBuffers* b) {
@@ -41,7 +50,10 @@ ga_status alloc_run(const ga_config* c, RunBuffers* b) {
   b->pop_b = reinterpret_cast<uint32_t*>(base + pop);
   b->keys_a = reinterpret_cast<uint32_t*>(base + 2 * pop);
   b->keys_b = reinterpret_cast<uint32_t*>(base + 2 * pop + keys);
-  b->sel = selects(c) ? reinterpret_cast<SelWork*>(base + 2 * pop + 2 * keys) : nullptr;
+  const size_t sel = selects(c) ? align256(sizeof(SelWork)) : 0;
+  b->sel = sel ? reinterpret_cast<SelWork*>(base + 2 * pop + 2 * keys) : nullptr;
+  b->slots = table_bytes(c) ? reinterpret_cast<uint32_t*>(base + 2 * pop + 2 * keys + sel)
+                            : nullptr;
   return GA_OK;
 }
 
@@ -49,6 +61,7 @@ PopDesc run_desc(const ga_config* c, const RunBuffers& b, RunState* st) {
   PopDesc d = make_desc(c, b.pop_a, b.pop_b, b.keys_a, b.keys_b, st, c->max_generations,
                         (c->flags & GA_STOP_ON_FOUND) ? 1u : 0u);
   d.sel = b.sel;
+  d.slots = b.slots;
   return d;
 }
 
@@ -150,12 +163,15 @@ ga_status MultiLaunch::set(const PopDesc* descs, uint32_t count,
 // Launch `node` of a chunk for one order group: the selections of its runs
 // that select (elitism, paper mode; each on its own workspace), then the
 // group's children launch.
-ga_status MultiLaunch::enqueue_group(const Group& g, uint32_t node, hipStream_t s) {
+ga_status MultiLaunch::enqueue_group(const Group& g, uint32_t node, bool tables,
+                                     hipStream_t s) {
   for (uint32_t i = 0; i < g.ndesc; ++i) {
     const PopDesc& d = g.hdesc[i];
-    if (d.sel)
-      GA_TRY(launch_select(d, d.paper ? d.n / 2 : d.elite, d.sel, node, nullptr, s),
-             "selection kernels");
+    if (!d.sel) continue;
+    const uint32_t* row =
+        (tables && d.paper && d.slots) ? d.slots + (size_t)node * (d.n / 2) : nullptr;
+    GA_TRY(launch_select(d, d.paper ? d.n / 2 : d.elite, d.sel, node, row, s),
+           "selection kernels");
   }
   GA_TRY(launch_children(g.desc, g.map, g.nblocks, g.m, g.lanes, node, s),
          "children kernel");
@@ -165,7 +181,7 @@ ga_status MultiLaunch::enqueue_group(const Group& g, uint32_t node, hipStream_t 
 ga_status MultiLaunch::enqueue_generation(uint32_t node, hipStream_t s) {
   for (Group& g : groups_) {
     if (!g.nblocks) continue;
-    const ga_status st = enqueue_group(g, node, s);
+    const ga_status st = enqueue_group(g, node, false, s);
     if (st != GA_OK) return st;
   }
   return GA_OK;
@@ -206,7 +222,14 @@ ga_status MultiLaunch::launch_chunk(uint32_t gens, hipStream_t s) {
       if (!gr.ndesc) continue;
       hipStream_t b = branch_[gi];
       st = hip_status(hipStreamWaitEvent(b, fork_[kOrders], 0), "hipStreamWaitEvent");
-      for (uint32_t i = 0; i < gens && st == GA_OK; ++i) st = enqueue_group(gr, i, b);
+      // paper-mode runs: the chunk's slot permutations first, in one launch each
+      const bool tables = gens <= kBatchTableRows;
+      for (uint32_t j = 0; j < gr.ndesc && st == GA_OK && tables; ++j) {
+        const PopDesc& d = gr.hdesc[j];
+        if (d.paper && d.slots)
+          st = hip_status(launch_perm_table(d, d.n / 2, gens, d.slots, b), "slot table kernel");
+      }
+      for (uint32_t i = 0; i < gens && st == GA_OK; ++i) st = enqueue_group(gr, i, tables, b);
       if (st == GA_OK)
         st = hip_status(launch_advance(gr.desc, gr.ndesc, gens, b),
                         "advance kernel");

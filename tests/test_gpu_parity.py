@@ -430,6 +430,8 @@ def _selecting_configs():
                   **paper),
         ga.Config(m=8, n=256, seed=67, fitness=ga.FIT_F2, nc=1, nr=1, max_generations=200,
                   flags=ga.STOP_ON_FOUND | ga.MUT_SHARED, **paper),
+        ga.Config(m=16, n=4000, seed=68, fitness=ga.FIT_F2, nc=2, nr=2, max_generations=45,
+                  flags=0, **paper),
     ]
 
 
