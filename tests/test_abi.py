@@ -99,6 +99,33 @@ def test_fitness_repeat_rejects_bad_repeat_counts():
     assert L.ga_fitness_repeat(ctypes.byref(cfg), None, fake, 5, None) == ga.GA_EINVAL
 
 
+def test_pack_unpack_reject_bad_arguments():
+    """Argument checks run before any device work: no GPU is touched."""
+    L = ga.lib()
+    fake = ctypes.c_void_p(256)            # never dereferenced: rejected first
+    good = ga.Config(m=20, n=10).c()
+    assert L.ga_pack(ctypes.byref(good), None, fake, None, None) == ga.GA_EINVAL
+    assert L.ga_pack(ctypes.byref(good), fake, None, None, None) == ga.GA_EINVAL
+    assert L.ga_unpack(ctypes.byref(good), None, fake, None) == ga.GA_EINVAL
+    assert L.ga_unpack(ctypes.byref(good), fake, None, None) == ga.GA_EINVAL
+    bad = ga.Config(m=132, n=10).c()
+    assert L.ga_pack(ctypes.byref(bad), fake, fake, None, None) == ga.GA_EINVAL
+    assert L.ga_unpack(ctypes.byref(bad), fake, fake, None) == ga.GA_EINVAL
+
+
+def test_batch_rejects_invalid_runs_before_device_work():
+    """ga_run_batch validates every config first (paper mode and elitism are
+    accepted, an invalid run is not), and needs results to write."""
+    L = ga.lib()
+    cfgs = (ga._Config * 2)(ga.Config(m=12, n=400, selection=ga.SEL_PAPER).c(),
+                            ga.Config(m=18, n=100).c())
+    outs = (ga._Result * 2)()
+    assert L.ga_run_batch(cfgs, 2, outs, None) == ga.GA_EINVAL
+    assert "m=18" in L.ga_last_error().decode()
+    assert L.ga_run_batch(cfgs, 0, outs, None) == ga.GA_EINVAL
+    assert L.ga_run_batch(cfgs, 2, None, None) == ga.GA_EINVAL
+
+
 def test_tuning_table_is_well_formed():
     """The committed lanes-per-child table: one row per order, allowed
     lanes only, increasing size limits with an open last entry."""
