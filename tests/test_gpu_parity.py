@@ -605,5 +605,6 @@ def test_invalid_configs_rejected():
     with pytest.raises(ga.GAError) as e:
         ga.ga_init_population(bad, pop)
     assert e.value.status == ga.GA_EINVAL
-    with pytest.raises(ga.GAError):
-        ga.ga_run_batch([ga.Config(m=8, n=100, elite=2)])
+    with pytest.raises(ga.GAError) as e:  # one invalid run rejects the batch
+        ga.ga_run_batch([ga.Config(m=8, n=100, elite=2), ga.Config(m=18, n=100)])
+    assert e.value.status == ga.GA_EINVAL
