@@ -74,7 +74,8 @@ MultiLaunch::~MultiLaunch() {
   if (graph_) (void)hipGraphExecDestroy(graph_);
   if (capture_) {
     (void)hipStreamDestroy(capture_);
-    for (auto b : branch_) (void)hipStreamDestroy(b);
+    for (auto b : branch_)
+      if (b) (void)hipStreamDestroy(b);
     for (auto e : fork_) (void)hipEventDestroy(e);
   }
   for (Group& g : groups_) {
@@ -206,13 +207,15 @@ ga_status MultiLaunch::launch_chunk(uint32_t gens, hipStream_t s) {
     if (!capture_) {
       GA_TRY(hipStreamCreateWithFlags(&capture_, hipStreamNonBlocking),
              "hipStreamCreate");
-      for (auto& b : branch_)
-        GA_TRY(hipStreamCreateWithFlags(&b, hipStreamNonBlocking),
-               "hipStreamCreate");
       for (auto& e : fork_)
         GA_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming),
                "hipEventCreate");
     }
+    // a capture branch only for the orders in use
+    for (int gi = 0; gi < kOrders; ++gi)
+      if (groups_[gi].ndesc && !branch_[gi])
+        GA_TRY(hipStreamCreateWithFlags(&branch_[gi], hipStreamNonBlocking),
+               "hipStreamCreate");
     hipGraph_t g;
     GA_TRY(hipStreamBeginCapture(capture_, hipStreamCaptureModeThreadLocal),
            "hipStreamBeginCapture");
