@@ -305,7 +305,12 @@ hipError_t launch_perm_table(const PopDesc& d, uint32_t count, uint32_t nodes,
 // copies the rows together, each lane issuing its loads before its stores.
 // With `fused`, the block sums the per-tile counts before its own tile (in
 // place of the one-block sel_offsets launch) and the grid clears h1 and h2.
-__global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a, uint32_t fused) {
+// `split` blocks share a tile: each lists the tile's selection, and block
+// `sub` of them copies rows sub, sub + split, ... of the list; the first
+// writes the keys.  Paper mode copies half of every tile, at large orders
+// megabytes per generation, which one block per tile would leave to few CUs.
+__global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a, uint32_t fused,
+                                                      uint32_t split) {
   uint32_t G;
   if (!sel_generation(a, &G)) return;
   const uint32_t g = G - 1;
@@ -315,10 +320,11 @@ __global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a, uint32_t fused)
   uint32_t* pout = odd ? a.pop_a : a.pop_b;
   uint32_t* kout = odd ? a.keys_a : a.keys_b;
   const uint32_t T = a.ws->T, r = a.ws->r;
+  const uint32_t tile = blockIdx.x / split, sub = blockIdx.x % split;
   uint32_t tile_less, tile_eq;
   if (fused) {
     uint32_t sl = 0, se = 0;
-    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kBlock) {
+    for (uint32_t b = threadIdx.x; b < tile; b += kBlock) {
       sl += a.ws->blk_less[b];
       se += a.ws->blk_eq[b];
     }
@@ -329,11 +335,11 @@ __global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a, uint32_t fused)
       a.ws->h2[i] = 0;
     }
   } else {
-    tile_less = a.ws->blk_less[blockIdx.x];
-    tile_eq = a.ws->blk_eq[blockIdx.x];
+    tile_less = a.ws->blk_less[tile];
+    tile_eq = a.ws->blk_eq[tile];
   }
   constexpr int PER = kSelTile / kBlock;  // consecutive keys per thread
-  const uint32_t i0 = blockIdx.x * kSelTile + threadIdx.x * PER;
+  const uint32_t i0 = tile * kSelTile + threadIdx.x * PER;
   uint32_t kk[PER];
   uint32_t cl = 0, ce = 0;
 #pragma unroll
@@ -376,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a, uint32_t fused)
     if (slots[e] != ~0u) {
       s_src[at] = i0 + e;
       s_dst[at] = slots[e];
-      kout[slots[e]] = kk[e];
+      if (sub == 0) kout[slots[e]] = kk[e];
       ++at;
     }
   }
@@ -393,16 +399,17 @@ __global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a, uint32_t fused)
     const uint32_t row = t / w4;
     return (size_t)s_dst[row] * w4 + (t - row * w4);
   };
-  uint32_t t = threadIdx.x;
-  for (; t + 3 * kBlock < items; t += 4 * kBlock) {  // four loads, then four stores
-    const uint4 v0 = src4[src_of(t)], v1 = src4[src_of(t + kBlock)];
-    const uint4 v2 = src4[src_of(t + 2 * kBlock)], v3 = src4[src_of(t + 3 * kBlock)];
+  const uint32_t S = split * kBlock;  // this block's words: sub * kBlock + tid + k S
+  uint32_t t = sub * kBlock + threadIdx.x;
+  for (; t + 3 * S < items; t += 4 * S) {  // four loads, then four stores
+    const uint4 v0 = src4[src_of(t)], v1 = src4[src_of(t + S)];
+    const uint4 v2 = src4[src_of(t + 2 * S)], v3 = src4[src_of(t + 3 * S)];
     dst4[dst_of(t)] = v0;
-    dst4[dst_of(t + kBlock)] = v1;
-    dst4[dst_of(t + 2 * kBlock)] = v2;
-    dst4[dst_of(t + 3 * kBlock)] = v3;
+    dst4[dst_of(t + S)] = v1;
+    dst4[dst_of(t + 2 * S)] = v2;
+    dst4[dst_of(t + 3 * S)] = v3;
   }
-  for (; t < items; t += kBlock) dst4[dst_of(t)] = src4[src_of(t)];
+  for (; t < items; t += S) dst4[dst_of(t)] = src4[src_of(t)];
 }
 
 hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
@@ -434,7 +441,11 @@ hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
   if (!fused) hipLaunchKernelGGL(sel_find, dim3(1), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(sel_count, dim3(gt), dim3(kBlock), 0, s, a, fused);
   if (!fused) hipLaunchKernelGGL(sel_offsets, dim3(1), dim3(kBlock), 0, s, a, gt);
-  hipLaunchKernelGGL(sel_scatter, dim3(gt), dim3(kBlock), 0, s, a, fused);
+  // paper mode copies half of every tile: one block per 32 words of a row
+  // shares each tile's copy (with the slot table; the inline walk would be
+  // repeated by every block of the tile)
+  const uint32_t split = (d.paper && slots) ? std::min<uint32_t>(16, cdiv(a.mw, 32)) : 1u;
+  hipLaunchKernelGGL(sel_scatter, dim3(gt * split), dim3(kBlock), 0, s, a, fused, split);
   return hipGetLastError();
 }
 

@@ -351,6 +351,9 @@ def test_run_plain_m8_config():
     ga.Config(m=12, n=400, seed=14, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
               xo_threshold=1 << 32, mut_threshold=1 << 32, nc=1, nr=1, max_generations=300,
               flags=ga.STOP_ON_FOUND | ga.MUT_SHARED),
+    ga.Config(m=52, n=2000, seed=18, selection=ga.SEL_PAPER, fitness=ga.FIT_F1,
+              xo_threshold=1 << 32, mut_threshold=1 << 32, nc=2, nr=3, max_generations=70,
+              flags=0),
     # 64 x 2N > 2^24: no chunk slot table, the scatter walks the permutation
     ga.Config(m=4, n=600000, seed=17, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
               xo_threshold=1 << 32, mut_threshold=1 << 32, nc=1, nr=1, max_generations=3,
