@@ -12,7 +12,9 @@ m = 8, n = 1,024 plain GA over 32 seeds.
 
 --workload batched: 24 runs in one batched launch per generation against
 the same 24 runs one after another.
---workload served: a Poisson stream of search requests through the server.
+--workload served: a Poisson stream of search requests through the server,
+then the first requests of the stream submitted at once against the same
+requests run one ga_run after another.
 --workload pmc: a short run for hardware-counter passes (no timing).
 --workload long_runs: the paper's single runs to a first Hadamard matrix
 (Sec. 4.4) with its population sizes and mutation counts.
@@ -421,6 +423,7 @@ def bench_served(args):
     srv.close()
     solved = [l for l, r in zip(lat, results) if r["found"]]
     evals = sum(c.n * (r["generation"] + 1) for c, r in zip(cfgs, results))
+    saturated = served_saturated(cfgs[:args.saturated]) if args.saturated > 0 else None
     return {
         "metric": "served search: requests/s and p50/p99 time-to-first-Hadamard",
         "value": count / wall, "unit": "requests/s", "n_gpus": 1, "steps": 1, "warmup": 0,
@@ -433,7 +436,51 @@ def bench_served(args):
         "time_to_first_hadamard": {"p50_s": percentile(solved, 50),
                                    "p99_s": percentile(solved, 99)},
         "time_to_retire": {"p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99)},
+        "saturated": saturated,
     }
+
+
+def same_result(a, b):
+    return (a["found"] == b["found"] and a["generation"] == b["generation"]
+            and a["index"] == b["index"] and a["best_key"] == b["best_key"]
+            and (a["matrix"] == b["matrix"]).all())
+
+
+def served_saturated(cfgs):
+    """The given requests submitted to a fresh server all at once, against the
+    same requests run one ga_run after another (each on buffers allocated
+    beforehand, after a warm pass that measures its lanes per child).  Both
+    sides make the same generations, so the generations/s ratio is the
+    ratio of wall times."""
+    import torch
+    import paper_2208_14961_amd as ga
+    srv = ga.Server(hbm_budget_bytes=200 * 10**9)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ids = [srv.submit(c) for c in cfgs]
+    served = [srv.wait(i) for i in ids]
+    dt_s = time.perf_counter() - t
+    srv.close()
+    print(f"served: saturated leg, {len(cfgs)} requests at once in {dt_s:.2f} s",
+          file=sys.stderr, flush=True)
+    bufs = [buffers(c) for c in cfgs]
+    for c, b in zip(cfgs, bufs):
+        ga.ga_run(c, *b)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain = [ga.ga_run(c, *b) for c, b in zip(cfgs, bufs)]
+    torch.cuda.synchronize()
+    dt_p = time.perf_counter() - t
+    del bufs
+    gens = sum(r["generation"] for r in served)
+    evals = sum(c.n * (r["generation"] + 1) for c, r in zip(cfgs, served))
+    return {"requests": len(cfgs), "generations": gens,
+            "server": {"seconds": dt_s, "generations_per_s": gens / dt_s,
+                       "evals_per_s": evals / dt_s},
+            "plain": {"seconds": dt_p, "generations_per_s": gens / dt_p,
+                      "evals_per_s": evals / dt_p},
+            "speedup_vs_plain": dt_p / dt_s,
+            "results_identical": all(same_result(a, b) for a, b in zip(served, plain))}
 
 
 # Average iterations to a Hadamard matrix over 10 runs per (NC, NR), rows
@@ -610,6 +657,9 @@ def main():
     ap.add_argument("--workload", default="default",
                     choices=["default", "batched", "served", "pmc", "paper_study", "table2", "long_runs"])
     ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--saturated", type=int, default=200,
+                    help="served: requests of the stream also submitted at once and "
+                         "run one by one (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--table2-orders", default="",
