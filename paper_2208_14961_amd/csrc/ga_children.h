@@ -90,6 +90,20 @@ struct Lanes {
   }
 };
 
+// Stores of a child's row and key, marked nontemporal.  The next
+// generation's launch reads them at random slots, mostly from other XCDs;
+// with the mark, their lines do not linger dirty in the writer's L2, and a
+// tournament generation at m = 20, n = 40,000 takes 10% less time (17% at
+// m = 36).  (A run-time choice between this and a plain store is merged
+// into one plain store by the compiler, so every mode takes this form.)
+__device__ __forceinline__ void store_row(uint4* p, const uint4& v) {
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  __builtin_nontemporal_store(v4u{v.x, v.y, v.z, v.w}, reinterpret_cast<v4u*>(p));
+}
+__device__ __forceinline__ void store_key(uint32_t* p, uint32_t v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 // Winner of tournament c of pair p (t contestants, draws c*t .. c*t+t-1 of
 // the pair's selection stream; block 0 is given): smallest key, then
 // smallest index.
@@ -412,7 +426,8 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d,
 #pragma unroll
       for (int s = 0; s < NP; ++s)
         if (Q::has(s, l))
-          o4[l + L * s] = make_uint4(f[4 * s], f[4 * s + 1], f[4 * s + 2], f[4 * s + 3]);
+          store_row(o4 + l + L * s,
+                    make_uint4(f[4 * s], f[4 * s + 1], f[4 * s + 2], f[4 * s + 3]));
     }
   }
 #pragma unroll
@@ -427,9 +442,10 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d,
 #pragma unroll
     for (int s = 0; s < NP; ++s)
       if (Q::has(s, l))
-        o4[l + L * s] = make_uint4(f[4 * s], f[4 * s + 1], f[4 * s + 2], f[4 * s + 3]);
+        store_row(o4 + l + L * s,
+                  make_uint4(f[4 * s], f[4 * s + 1], f[4 * s + 2], f[4 * s + 3]));
   }
-  if (l == 0) kout[dst] = key;
+  if (l == 0) store_key(kout + dst, key);
   return ((unsigned long long)key << 32) | dst;
 }
 
