@@ -90,18 +90,27 @@ struct Lanes {
   }
 };
 
-// Stores of a child's row and key, marked nontemporal.  The next
-// generation's launch reads them at random slots, mostly from other XCDs;
-// with the mark, their lines do not linger dirty in the writer's L2, and a
-// tournament generation at m = 20, n = 40,000 takes 10% less time (17% at
-// m = 36).  (A run-time choice between this and a plain store is merged
-// into one plain store by the compiler, so every mode takes this form.)
+// Stores of a child's row and key: nontemporal when NT.  A single run's next
+// launch reads them at random slots, mostly from other XCDs; with the mark
+// their lines do not linger dirty in the writer's L2, and a tournament
+// generation at m = 20, n = 40,000 takes 10% less time (17% at m = 36).
+// The batched launch measured 7% slower with the mark, so it stores plainly.
+// (The choice is made at compile time: a run-time choice between the two
+// stores is merged into one plain store by the compiler.)
+template <bool NT>
 __device__ __forceinline__ void store_row(uint4* p, const uint4& v) {
   typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-  __builtin_nontemporal_store(v4u{v.x, v.y, v.z, v.w}, reinterpret_cast<v4u*>(p));
+  if constexpr (NT)
+    __builtin_nontemporal_store(v4u{v.x, v.y, v.z, v.w}, reinterpret_cast<v4u*>(p));
+  else
+    *p = v;
 }
+template <bool NT>
 __device__ __forceinline__ void store_key(uint32_t* p, uint32_t v) {
-  __builtin_nontemporal_store(v, p);
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
 }
 
 // Winner of tournament c of pair p (t contestants, draws c*t .. c*t+t-1 of
@@ -352,8 +361,8 @@ __device__ __forceinline__ uint32_t lanes_fitness(const uint32_t* me, uint32_t l
 
 // The child of this lane's group in generation G; `lds` holds the block's
 // children (M*W words each).  Lanes of pairs past the last compute a copy of
-// the last pair and store nothing.
-template <int M, uint32_t NEED, int L_>
+// the last pair and store nothing.  NT: nontemporal stores of the child.
+template <int M, uint32_t NEED, int L_, bool NT>
 __device__ __forceinline__ unsigned long long child(const PopDesc& d,
                                                    uint32_t G, uint32_t* lds) {
   using Q = Lanes<M, L_>;
@@ -426,7 +435,7 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d,
 #pragma unroll
       for (int s = 0; s < NP; ++s)
         if (Q::has(s, l))
-          store_row(o4 + l + L * s,
+          store_row<NT>(o4 + l + L * s,
                     make_uint4(f[4 * s], f[4 * s + 1], f[4 * s + 2], f[4 * s + 3]));
     }
   }
@@ -442,10 +451,10 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d,
 #pragma unroll
     for (int s = 0; s < NP; ++s)
       if (Q::has(s, l))
-        store_row(o4 + l + L * s,
+        store_row<NT>(o4 + l + L * s,
                   make_uint4(f[4 * s], f[4 * s + 1], f[4 * s + 2], f[4 * s + 3]));
   }
-  if (l == 0) store_key(kout + dst, key);
+  if (l == 0) store_key<NT>(kout + dst, key);
   return ((unsigned long long)key << 32) | dst;
 }
 
@@ -478,7 +487,7 @@ __global__ __launch_bounds__(kChildBlock) void children_one_kernel(PopDesc d,
   using Q = Lanes<M, L>;
   __shared__ __align__(16) uint32_t lds[Q::CPB * M * Q::W];
   children_block(d, node, [&](uint32_t G) __attribute__((always_inline)) {
-    return child<M, NEED, L>(d, G, lds);
+    return child<M, NEED, L, true>(d, G, lds);
   });
 }
 
@@ -496,7 +505,7 @@ __global__ __launch_bounds__(kChildBlock) void children_multi_kernel(
   __shared__ __align__(16) uint32_t lds[Q::CPB * M * Q::W];
   const PopDesc d = descs[block_pop[blockIdx.x]];
   children_block(d, node, [&](uint32_t G) __attribute__((always_inline)) {
-    return child<M, 0, L>(d, G, lds);
+    return child<M, 0, L, false>(d, G, lds);
   });
 }
 
