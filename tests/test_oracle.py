@@ -359,6 +359,170 @@ def test_step_paper_mode():
     assert keys2[: 2 * N].max() <= np.sort(keys)[2 * N - 1]
 
 
+# --------------------------------------------------------------------------
+# The pair operator of a generation: crossover cut, parent orientation, coins
+# --------------------------------------------------------------------------
+def _cut_of(A, B, C0, C1):
+    """The cut c in [1, m-1] with C0 = A[:, <c] | B[:, >=c] and
+    C1 = B[:, <c] | A[:, >=c], or None when no cut explains the children.
+    Meant for parents whose columns 1..m-1 all differ, where such a cut is
+    unique (column 0 is all +1 in both, so c = 0 would equal c = 1)."""
+    m = A.shape[0]
+    for c in range(1, m):
+        if (np.array_equal(C0[:, :c], A[:, :c]) and np.array_equal(C0[:, c:], B[:, c:])
+                and np.array_equal(C1[:, :c], B[:, :c]) and np.array_equal(C1[:, c:], A[:, c:])):
+            return c
+    return None
+
+
+def _distinct_columns(A, B):
+    return all(not np.array_equal(A[:, j], B[:, j]) for j in range(1, A.shape[0]))
+
+
+def _tournament_pairs(cfg, pop, keys, gen_in):
+    """(pair, parent a, parent b) of every child pair of a tournament step."""
+    return [(p, *gao.tournament_parents(cfg, keys, gen_in + 1, p))
+            for p in range((cfg.n - cfg.elite + 1) // 2)]
+
+
+def _uniform_cut_ok(cuts, m):
+    """Chi-square goodness of fit of the cuts to the uniform law on [1, m-1]."""
+    counts = np.bincount(np.asarray(cuts), minlength=m)[1:]
+    assert counts.sum() == len(cuts)
+    return stats.chisquare(counts).pvalue > 1e-4
+
+
+@pytest.mark.parametrize("m", [8, 20, 36])
+def test_tournament_crossover_cut_range_and_orientation(m):
+    """With the crossover coin always on and no mutation, child 0 of pair p
+    is a[:, <c] | b[:, >=c] and child 1 the complement, for one cut c, where a
+    is the parent of the first tournament and b of the second (Sec. 3.4:
+    each part of one parent is joined with the adjoining part of the other);
+    the cut is uniform over [1, m-1] (the listing's random_integers(1, m-1)).
+    A swapped parent order, a missing complement, a cut range of [0, m-1]
+    (c = 0 looks like c = 1 here and doubles its count) or [1, m-2] fails."""
+    cfg = gao.Config(m=m, n=12000, seed=40 + m, xo_threshold=1 << 32, mut_threshold=0, nc=0,
+                     nr=0, tournament_k=2)
+    pop = inputs.random_population(m, cfg.n, seed=m)
+    keys = gao.fitness(cfg, pop)
+    pop2, _ = gao.step(cfg, pop, keys, 0)
+    cuts = []
+    for p, a, b in _tournament_pairs(cfg, pop, keys, 0):
+        if a == b or not _distinct_columns(pop[a], pop[b]):
+            continue
+        c = _cut_of(pop[a], pop[b], pop2[2 * p], pop2[2 * p + 1])
+        assert c is not None, p
+        cuts.append(c)
+    assert len(cuts) > 5000
+    assert _uniform_cut_ok(cuts, m)
+
+
+@pytest.mark.parametrize("m", [8, 20])
+def test_paper_mode_crossover_orientation(m):
+    """Paper mode (Sec. 3.4, the crossover figure): offspring slot 2N + k
+    takes the columns before the cut from parent P_k and the rest from
+    P_{k+N}; slot 3N + k takes the columns before the cut from P_{k+N}.  The
+    cut is drawn for every pair, uniform over [1, m-1]."""
+    N = 3000
+    cfg = gao.Config(m=m, n=4 * N, seed=70 + m, selection=gao.SEL_PAPER, fitness=gao.FIT_F2,
+                     xo_threshold=1 << 32, mut_threshold=0, nc=0, nr=0)
+    pop = inputs.random_population(m, cfg.n, seed=100 + m)
+    keys = gao.fitness(cfg, pop)
+    pop2, _ = gao.step(cfg, pop, keys, 0)
+    cuts = []
+    for k in range(N):
+        P, Q = pop2[k], pop2[k + N]
+        if not _distinct_columns(P, Q):
+            continue
+        c = _cut_of(P, Q, pop2[2 * N + k], pop2[3 * N + k])
+        assert c is not None, k
+        cuts.append(c)
+    assert len(cuts) > N // 2
+    assert _uniform_cut_ok(cuts, m)
+
+
+def test_no_crossover_no_mutation_children_copy_parents():
+    """Both coins off: child 0 of pair p is parent a and child 1 parent b in
+    tournament mode; in paper mode offspring 2N + k is P_k and 3N + k is
+    P_{k+N}."""
+    m = 12
+    cfg = gao.Config(m=m, n=801, seed=5, xo_threshold=0, mut_threshold=0, nc=0, nr=0, elite=3)
+    pop = inputs.random_population(m, cfg.n, seed=1)
+    keys = gao.fitness(cfg, pop)
+    pop2, keys2 = gao.step(cfg, pop, keys, 4)
+    for p, a, b in _tournament_pairs(cfg, pop, keys, 4):
+        for ch, par in ((0, a), (1, b)):
+            s = cfg.elite + 2 * p + ch
+            if s < cfg.n:
+                assert np.array_equal(pop2[s], pop[par]) and keys2[s] == keys[par]
+    N = 200
+    pc = gao.Config(m=m, n=4 * N, seed=6, selection=gao.SEL_PAPER, xo_threshold=0,
+                    mut_threshold=0, nc=0, nr=0)
+    pop = inputs.random_population(m, pc.n, seed=2)
+    keys = gao.fitness(pc, pop)
+    pop2, _ = gao.step(pc, pop, keys, 0)
+    assert np.array_equal(pop2[2 * N:3 * N], pop2[:N])
+    assert np.array_equal(pop2[3 * N:], pop2[N:2 * N])
+
+
+def _binomial_ok(count, trials, rate):
+    return stats.binomtest(count, trials, rate).pvalue > 1e-4
+
+
+@pytest.mark.parametrize("num,den", [(1, 2), (1, 10), (3, 4)])
+def test_crossover_coin_rate(num, den):
+    """The crossover coin of a pair succeeds with the configured rate (the
+    benchmark configurations use 0.5): over pairs whose parents differ in
+    every column, the fraction of pairs whose children are not the parents
+    copied is binomial with that rate."""
+    m = 16
+    cfg = gao.Config(m=m, n=16000, seed=den, xo_threshold=gao.rate_threshold(num, den),
+                     mut_threshold=0, nc=0, nr=0)
+    pop = inputs.random_population(m, cfg.n, seed=7)
+    keys = gao.fitness(cfg, pop)
+    pop2, _ = gao.step(cfg, pop, keys, 2)
+    crossed = trials = 0
+    for p, a, b in _tournament_pairs(cfg, pop, keys, 2):
+        if a == b or not _distinct_columns(pop[a], pop[b]):
+            continue
+        trials += 1
+        same = np.array_equal(pop2[2 * p], pop[a]) and np.array_equal(pop2[2 * p + 1], pop[b])
+        if not same:
+            assert _cut_of(pop[a], pop[b], pop2[2 * p], pop2[2 * p + 1]) is not None
+            crossed += 1
+    assert trials > 7000
+    assert _binomial_ok(crossed, trials, num / den), (crossed, trials)
+
+
+@pytest.mark.parametrize("num,den", [(1, 10), (1, 2)])
+def test_mutation_coin_rate_per_child(num, den):
+    """Each child is mutated with the configured probability (0.1 in the
+    benchmark configurations), independently of its sibling: with the
+    crossover off and 64 row pairs per mutated child (a mutated column is
+    then left unchanged with negligible probability), the children that
+    differ from their parent are binomial with that rate, and both children
+    of a pair are mutated at the rate's square."""
+    m = 16
+    cfg = gao.Config(m=m, n=20000, seed=11 + den, xo_threshold=0,
+                     mut_threshold=gao.rate_threshold(num, den), nc=1, nr=64)
+    pop = inputs.random_population(m, cfg.n, seed=8)
+    keys = gao.fitness(cfg, pop)
+    pop2, _ = gao.step(cfg, pop, keys, 0)
+    changed, both, pairs = 0, 0, 0
+    for p, a, b in _tournament_pairs(cfg, pop, keys, 0):
+        c0 = not np.array_equal(pop2[2 * p], pop[a])
+        c1 = not np.array_equal(pop2[2 * p + 1], pop[b])
+        changed += c0 + c1
+        both += c0 and c1
+        pairs += 1
+        for ch, par in ((0, a), (1, b)):
+            diff = np.argwhere(pop2[2 * p + ch] != pop[par])
+            assert len(set(diff[:, 1].tolist())) <= 1   # one column (nc = 1)
+    rate = num / den
+    assert _binomial_ok(changed, 2 * pairs, rate), (changed, 2 * pairs)
+    assert _binomial_ok(both, pairs, rate * rate), (both, pairs)
+
+
 def test_run_finds_hadamard_m4_and_m8():
     for m in (4, 8):
         cfg = gao.Config(m=m, n=256, seed=0, max_generations=200)
