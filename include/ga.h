@@ -63,7 +63,8 @@ typedef enum {
   GA_ENOMEM = -2,     /* device allocation failed                            */
   GA_EDEVICE = -3,    /* a HIP call failed; see ga_last_error()              */
   GA_EBUDGET = -4,    /* a request can never fit the server's HBM budget     */
-  GA_ENOTFOUND = -5   /* unknown request id                                  */
+  GA_ENOTFOUND = -5,  /* unknown request id                                  */
+  GA_ESTOPPED = -6    /* the server has stopped (ga_server_stop)             */
 } ga_status;
 
 typedef enum {
@@ -114,7 +115,7 @@ typedef struct {
   uint64_t mut_threshold;   /* per-child mutation coin threshold, <= 2^32    */
   uint32_t nc;              /* mutated columns per mutated child, <= 64      */
   uint32_t nr;              /* row pairs per mutated child, <= 64            */
-  uint32_t max_generations; /* generation budget of ga_run                   */
+  uint32_t max_generations; /* generation budget of ga_run, < 2^31          */
   uint32_t flags;           /* GA_STOP_ON_FOUND | GA_MUT_SHARED |
                                lanes << GA_LANES_SHIFT                       */
 } ga_config;
@@ -274,7 +275,9 @@ ga_status ga_timing_read(double* mean_ms, uint64_t* launches);
 /* -------------------------------------------------------------------------
  * Search server: continuous batching of independent runs (every selection
  * mode, as ga_run_batch).
- * Requests are admitted while their device memory fits the HBM budget;
+ * Requests are admitted in arrival order among those whose device memory
+ * fits the HBM budget (one that does not fit is passed over by at most 64
+ * later admissions, then waited for);
  * admitted populations stay resident on the device and advance one
  * generation per server tick together with every other active request; a
  * request retires when a key reaches 0 (with GA_STOP_ON_FOUND) or its
@@ -285,7 +288,10 @@ typedef struct ga_server ga_server;
 /* Starts the server's worker thread on `device`.  *out: new handle. */
 ga_status ga_server_create(uint64_t hbm_budget_bytes, int device,
                            ga_server** out);
-/* Non-blocking.  GA_EBUDGET if the request alone exceeds the budget. */
+/* Non-blocking.  GA_EBUDGET if the request alone exceeds the budget.  Once
+ * the worker has stopped, every submission is refused with its terminal
+ * status: GA_ESTOPPED after ga_server_stop, the device error's status
+ * (GA_EDEVICE, GA_ENOMEM) if one ended it. */
 ga_status ga_submit(ga_server* srv, const ga_config* cfg, uint64_t* request_id);
 /* GA_PENDING while running, GA_OK once *out holds the result. */
 ga_status ga_poll(ga_server* srv, uint64_t request_id, ga_result* out);
@@ -294,7 +300,12 @@ ga_status ga_wait(ga_server* srv, uint64_t request_id, ga_result* out);
 /* Seconds from submission to retirement of a finished request. */
 ga_status ga_request_latency(ga_server* srv, uint64_t request_id,
                              double* seconds);
-/* Stops the worker (pending requests are abandoned) and frees memory. */
+/* Stops the worker: requests not yet finished fail with GA_ESTOPPED (a
+ * device error ends the worker the same way, with its own status); finished
+ * results stay readable with ga_poll / ga_wait until ga_server_destroy.
+ * Blocks until the worker has exited. */
+ga_status ga_server_stop(ga_server* srv);
+/* Stops the worker as ga_server_stop does and frees the server. */
 ga_status ga_server_destroy(ga_server* srv);
 
 #ifdef __cplusplus

@@ -26,7 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libga.so")
 
 GA_OK, GA_PENDING = 0, 1
-GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_EBUDGET, GA_ENOTFOUND = -1, -2, -3, -4, -5
+GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_EBUDGET, GA_ENOTFOUND, GA_ESTOPPED = -1, -2, -3, -4, -5, -6
 FIT_SQ, FIT_ABS, FIT_NNZ, FIT_SQ_PLUS_NNZ, FIT_F1, FIT_F2 = range(6)
 SEL_TOURNAMENT, SEL_PAPER = 0, 1
 STOP_ON_FOUND = 1
@@ -138,6 +138,7 @@ def lib() -> ctypes.CDLL:
             "ga_poll": (i32, [vp, u64, P(_Result)]),
             "ga_wait": (i32, [vp, u64, P(_Result)]),
             "ga_request_latency": (i32, [vp, u64, P(ctypes.c_double)]),
+            "ga_server_stop": (i32, [vp]),
             "ga_server_destroy": (i32, [vp]),
             "ga_timing_enable": (i32, [i32]),
             "ga_timing_read": (i32, [P(ctypes.c_double), P(u64)]),
@@ -283,7 +284,8 @@ def ga_timing_read():
 
 
 class Server:
-    """ga_server_create / ga_submit / ga_poll / ga_wait / ga_server_destroy."""
+    """ga_server_create / ga_submit / ga_poll / ga_wait / ga_server_stop /
+    ga_server_destroy."""
 
     def __init__(self, hbm_budget_bytes: int, device: int = 0):
         self._h = ctypes.c_void_p()
@@ -310,6 +312,11 @@ class Server:
         s = ctypes.c_double()
         _check(lib().ga_request_latency(self._h, rid, ctypes.byref(s)))
         return s.value
+
+    def stop(self) -> None:
+        """Stops the worker: unfinished requests fail with GA_ESTOPPED, and
+        later submissions are refused; finished results stay readable."""
+        _check(lib().ga_server_stop(self._h))
 
     def close(self) -> None:
         if self._h:

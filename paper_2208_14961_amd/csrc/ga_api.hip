@@ -58,6 +58,10 @@ ga_status validate(const ga_config* c) {
     set_error("n=%u: need 2 <= n <= %u", c->n, kMaxN);
     return GA_EINVAL;
   }
+  if (c->max_generations > kMaxGenerations) {
+    set_error("max_generations=%u: need at most %u", c->max_generations, kMaxGenerations);
+    return GA_EINVAL;
+  }
   if (c->fitness > GA_FIT_F2 || c->selection > GA_SEL_PAPER) {
     set_error("unknown fitness (%u) or selection (%u)", c->fitness,
               c->selection);
@@ -417,7 +421,7 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
   // the gen_base advance, replayed.  The host reads the state of chunk k
   // while chunk k+1 runs; launches past the end of the run return at once.
   const uint32_t chunk = std::min<uint32_t>(64, std::max<uint32_t>(1, cfg->max_generations));
-  const uint32_t nchunks = (cfg->max_generations + chunk - 1) / chunk;
+  const uint32_t nchunks = (uint32_t)(((uint64_t)cfg->max_generations + chunk - 1) / chunk);
   // Paper mode: the chunk's slot permutations are computed by one launch at
   // its start (when the table stays small), not inside each scatter.
   const uint32_t D = cfg->selection == GA_SEL_PAPER ? cfg->n / 2 : 0;
@@ -551,7 +555,8 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
                                ? w->host_state[0] : w->host_state[1];
       uint32_t made = std::min(cfg->max_generations, hs.gen_base);
       if (stop_on_found && hs.found_gen < made) made = hs.found_gen;
-      const uint32_t before = std::min(cfg->max_generations, first * chunk);
+      const uint32_t before = (uint32_t)std::min<uint64_t>(cfg->max_generations,
+                                                           (uint64_t)first * chunk);
       g_timing.total_ms += ms;
       g_timing.gens += made > before ? made - before : 0;
     }

@@ -30,6 +30,9 @@ inline uint64_t max_key(uint32_t m, uint32_t kind) {
 
 constexpr uint32_t kMaxN = 1u << 24;        // population size limit
 constexpr uint32_t kMaxElite = 1u << 16;    // elite count limit
+// generation budget limit: generation numbers up to the budget plus two
+// chunks of launches stay below 2^32
+constexpr uint32_t kMaxGenerations = 0x7fffffffu;
 constexpr uint32_t kKeyBits = 24;           // selection ranks keys < 2^24
 constexpr int kBlock = 256;                 // threads per block, bulk kernels
 constexpr int kChildBlock = 64;             // one wave per block: children

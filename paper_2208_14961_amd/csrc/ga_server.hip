@@ -1,12 +1,17 @@
 // ga_server.hip -- search server: continuous batching of independent runs.
 //
 // A worker thread owns one stream on the server's device.  Each tick it
-// admits pending requests in arrival order while their device memory fits
-// the HBM budget (and a run-state slot is free), starts them, advances every
-// active run by a few generations with one children launch per generation
-// covering all of them, then retires the runs whose state says stop.  Runs
-// never share buffers, and every random draw is keyed by the run's own seed,
-// so a request's result does not depend on what else is in flight.
+// admits pending requests in arrival order, those whose device memory fits
+// the HBM budget (and while a run-state slot is free), starts them, advances
+// every active run by a few generations with one children launch per
+// generation covering all of them, then retires the runs whose state says
+// stop.  A pending request that does not fit is passed over by later ones
+// that do, at most kMaxBypass times; after that admission waits for it.
+// Runs never share buffers, and every random draw is keyed by the run's own
+// seed, so a request's result does not depend on what else is in flight.
+// When the worker stops (ga_server_stop, or a device error) every request
+// not yet finished fails, and later submissions are refused with the
+// worker's terminal status.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,6 +20,7 @@
 #include <deque>
 #include <memory>
 #include <mutex>
+#include <queue>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -26,6 +32,7 @@ namespace ga {
 
 constexpr uint32_t kServerSlots = 4096;    // runs resident at once
 constexpr uint32_t kGensPerTick = 4;       // generations between retire checks
+constexpr uint32_t kMaxBypass = 64;        // admissions past a waiting request
 
 static double now_s() {
   using namespace std::chrono;
@@ -39,6 +46,8 @@ struct Request {
   double t_submit = 0, t_done = 0;
   RunBuffers buf;
   uint32_t slot = 0;
+  // the server's admission count when this request was first passed over
+  uint64_t passed_at = ~0ull;
   enum { kPending, kActive, kDone } phase = kPending;
   ga_status status = GA_OK;
   std::string error;
@@ -56,11 +65,16 @@ struct ga_server {
   std::unordered_map<uint64_t, std::unique_ptr<ga::Request>> reqs;
   uint64_t next_id = 1;
   uint64_t used = 0;
+  uint64_t admissions = 0;  // requests admitted so far
   bool quit = false;
   std::thread worker;
   ga_status start_status = GA_OK;
   std::string start_error;
   bool started = false;
+  // set when the worker has stopped: the status later submissions get
+  ga_status stop_status = GA_OK;
+  std::string stop_error;
+  bool stopped = false;
 };
 
 namespace ga {
@@ -97,8 +111,10 @@ static void worker_main(ga_server* S) {
     S->started = true;
     S->cv_done.notify_all();
   }
-  std::vector<uint32_t> free_slots;
-  for (uint32_t i = 0; i < kServerSlots; ++i) free_slots.push_back(kServerSlots - 1 - i);
+  // free run-state slots, lowest first, so that the occupied ones stay
+  // packed at the front and each tick copies only that range
+  std::priority_queue<uint32_t, std::vector<uint32_t>, std::greater<uint32_t>> free_slots;
+  for (uint32_t i = 0; i < kServerSlots; ++i) free_slots.push(i);
   std::vector<Request*> active;
   MultiLaunch ml;
   bool changed = false;
@@ -107,11 +123,20 @@ static void worker_main(ga_server* S) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
       if (S->quit) break;
-      while (!S->pending.empty() && active.size() + admit.size() < kServerSlots) {
-        Request* r = S->reqs[S->pending.front()].get();
-        if (S->used + r->bytes > S->budget) break;  // arrival order is kept
-        S->pending.pop_front();
+      // arrival order among the requests that fit; one that does not fit
+      // is passed over, up to kMaxBypass times, then waited for
+      for (auto it = S->pending.begin();
+           it != S->pending.end() && active.size() + admit.size() < kServerSlots;) {
+        Request* r = S->reqs[*it].get();
+        if (S->used + r->bytes > S->budget) {
+          if (r->passed_at == ~0ull) r->passed_at = S->admissions;
+          if (S->admissions - r->passed_at >= kMaxBypass) break;
+          ++it;
+          continue;
+        }
+        it = S->pending.erase(it);
         S->used += r->bytes;
+        ++S->admissions;
         admit.push_back(r);
       }
       if (active.empty() && admit.empty()) {
@@ -122,8 +147,8 @@ static void worker_main(ga_server* S) {
     for (Request* r : admit) {
       ga_status a = alloc_run(&r->cfg, &r->buf);
       if (a == GA_OK) {
-        r->slot = free_slots.back();
-        free_slots.pop_back();
+        r->slot = free_slots.top();
+        free_slots.pop();
         a = start_runs(&r->cfg, &r->buf, &states[r->slot], 1, stream);
       }
       if (a != GA_OK) {
@@ -131,7 +156,10 @@ static void worker_main(ga_server* S) {
         finish(S, r, a, ga_last_error());
         continue;
       }
-      r->phase = Request::kActive;
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        r->phase = Request::kActive;
+      }
       active.push_back(r);
       changed = true;
     }
@@ -145,7 +173,9 @@ static void worker_main(ga_server* S) {
     }
     st = ml.launch_chunk(kGensPerTick, stream);
     if (st != GA_OK) break;
-    st = hip_status(hipMemcpyAsync(host, states, kServerSlots * sizeof(RunState),
+    uint32_t used_slots = 0;
+    for (Request* r : active) used_slots = std::max(used_slots, r->slot + 1);
+    st = hip_status(hipMemcpyAsync(host, states, used_slots * sizeof(RunState),
                                    hipMemcpyDeviceToHost, stream),
                     "hipMemcpyAsync(states)");
     if (st == GA_OK)
@@ -171,29 +201,37 @@ static void worker_main(ga_server* S) {
         rr = read_result(&r->cfg, host[r->slot], r->buf.pop_a, r->buf.pop_b,
                          &r->result);
       free_run(&r->buf);
-      free_slots.push_back(r->slot);
+      free_slots.push(r->slot);
       finish(S, r, rr, rr == GA_OK ? nullptr : ga_last_error());
       changed = true;
     }
     active.swap(still);
   }
-  // a device error ends the worker: fail everything still queued or running
-  const std::string err = st == GA_OK ? "" : ga_last_error();
+  // a stop request or a device error ends the worker: everything still
+  // queued or running fails with that status, and so does every later
+  // submission (recorded in the same critical section that empties the
+  // queue, so a submission either lands before it and fails here, or sees
+  // the status)
+  const ga_status end = st == GA_OK ? GA_ESTOPPED : st;
+  const std::string err = st == GA_OK ? "server stopped" : ga_last_error();
   if (stream) (void)hipStreamSynchronize(stream);
   for (Request* r : active) {
     free_run(&r->buf);
-    finish(S, r, st == GA_OK ? GA_EDEVICE : st,
-           st == GA_OK ? "server stopped" : err.c_str());
+    finish(S, r, end, err.c_str());
   }
   {
     std::lock_guard<std::mutex> lk(S->mu);
     for (uint64_t id : S->pending) {
       Request* r = S->reqs[id].get();
-      r->status = GA_EDEVICE;
-      r->error = st == GA_OK ? "server stopped" : err;
+      r->status = end;
+      r->error = err;
+      r->t_done = now_s();
       r->phase = Request::kDone;
     }
     S->pending.clear();
+    S->stop_status = end;
+    S->stop_error = err;
+    S->stopped = true;
     S->cv_done.notify_all();
   }
   if (states) (void)hipFree(states);
@@ -260,6 +298,10 @@ ga_status ga_submit(ga_server* S, const ga_config* cfg, uint64_t* request_id) {
   r->bytes = bytes;
   r->t_submit = now_s();
   std::lock_guard<std::mutex> lk(S->mu);
+  if (S->stopped) {
+    set_error("the server has stopped: %s", S->stop_error.c_str());
+    return S->stop_status;
+  }
   r->id = S->next_id++;
   *request_id = r->id;
   S->pending.push_back(r->id);
@@ -315,17 +357,30 @@ ga_status ga_request_latency(ga_server* S, uint64_t id, double* seconds) {
   return GA_OK;
 }
 
-ga_status ga_server_destroy(ga_server* S) {
-  if (!S) {
-    set_error("server is NULL");
-    return GA_EINVAL;
-  }
+static void stop_worker(ga_server* S) {
   {
     std::lock_guard<std::mutex> lk(S->mu);
     S->quit = true;
     S->cv_work.notify_all();
   }
-  S->worker.join();
+  if (S->worker.joinable()) S->worker.join();
+}
+
+ga_status ga_server_stop(ga_server* S) {
+  if (!S) {
+    set_error("server is NULL");
+    return GA_EINVAL;
+  }
+  stop_worker(S);
+  return GA_OK;
+}
+
+ga_status ga_server_destroy(ga_server* S) {
+  if (!S) {
+    set_error("server is NULL");
+    return GA_EINVAL;
+  }
+  stop_worker(S);
   delete S;
   return GA_OK;
 }

@@ -51,6 +51,8 @@ def test_population_words():
     # C(m-1, 2) m^2 >= 2^24 from order 80 on)
     dict(m=80, n=100, elite=1), dict(m=80, n=100, elite=1, fitness=ga.FIT_SQ_PLUS_NNZ),
     dict(m=128, n=400, selection=ga.SEL_PAPER, fitness=ga.FIT_SQ),
+    # generation budgets whose generation numbers could pass 2^32
+    dict(max_generations=1 << 31), dict(max_generations=(1 << 32) - 1),
 ])
 def test_invalid_configs(kw):
     base = dict(m=8, n=10)
@@ -77,7 +79,8 @@ def test_valid_configs():
                                                           fitness=ga.FIT_SQ_PLUS_NNZ),
                 ga.Config(m=128, n=100, elite=1, fitness=ga.FIT_ABS),
                 ga.Config(m=100, n=40000, selection=ga.SEL_PAPER, fitness=ga.FIT_F1,
-                          xo_threshold=1 << 32, mut_threshold=1 << 32, nc=4, nr=2)]:
+                          xo_threshold=1 << 32, mut_threshold=1 << 32, nc=4, nr=2),
+                ga.Config(m=8, n=10, max_generations=(1 << 31) - 1)]:
         assert ga.ga_validate(cfg), cfg
 
 
@@ -155,3 +158,16 @@ def test_tuned_lanes_query():
     assert ga.ga_tuned_lanes(ga.Config(m=100, n=40000)) in (8, 16)
     assert ga.ga_tuned_lanes(ga.Config(m=128, n=40000, flags=ga.lanes_flag(8))) == 8
     assert ga.ga_tuned_lanes(ga.Config(m=6, n=100)) == 0
+
+
+def test_run_rejects_unbounded_budget_before_device_work():
+    """A budget of 2^32 - 1 generations (a natural 'until found' value) is
+    rejected by ga_run itself before any device work, instead of wrapping
+    its chunk count."""
+    L = ga.lib()
+    fake = ctypes.c_void_p(256)            # never dereferenced: rejected first
+    cfg = ga.Config(m=8, n=10, max_generations=(1 << 32) - 1).c()
+    out = ga._Result()
+    assert L.ga_run(ctypes.byref(cfg), fake, ctypes.c_void_p(512), fake,
+                    ctypes.c_void_p(512), ctypes.byref(out), None) == ga.GA_EINVAL
+    assert "max_generations" in L.ga_last_error().decode()
