@@ -7,8 +7,11 @@ fitness SQ (and, timed beside it, ABS), binary tournament, crossover 0.5,
 one pair flip per child at rate 0.1, stop-on-found off.  Prints one JSON
 line with the throughput in evaluations per second (n fitness evaluations
 per generation plus the initial population), the roofline of the fused
-children kernel, the oracle's CPU throughput and the time-to-solve of the
-m = 8, n = 1,024 plain GA over 32 seeds.
+children kernel, the oracle's CPU throughput (all cores and one thread),
+the time-to-solve of the m = 8, n = 1,024 plain GA over 32 seeds, and
+summaries of the batched workload (24 runs against one ga_run each) and of
+the served workload (the Poisson stream of 2,000 requests, then its first
+200 requests at once against one ga_run each).
 
 --workload batched: 24 runs in one batched launch per generation against
 the same 24 runs one after another.
@@ -29,6 +32,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -114,26 +118,54 @@ def timed_runs(cfg, bufs, steps):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(m, n, seed, kind, budget_s=15.0):
-    """The oracle (plain C, OpenMP over individuals) on a bounded sample of
-    the same workload: init, fitness and as many generations as fit in about
-    budget_s seconds."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def oracle_rate(m, n, seed, kind, budget_s, max_gens=500):
+    """The oracle on init, fitness and as many generations of the workload as
+    fit in about budget_s seconds: (evals/s, generations, seconds)."""
     from oracle import gao
-    probe = gao.Config(m=m, n=n, seed=seed, fitness=kind, max_generations=2,
+    probe = gao.Config(m=m, n=n, seed=seed, fitness=kind, max_generations=1,
                        stop_on_found=False)
     t = time.perf_counter()
     gao.run(probe)
-    per_gen = (time.perf_counter() - t) / 3
-    gens = max(2, min(500, int(budget_s / max(per_gen, 1e-6)) - 1))
+    per_gen = (time.perf_counter() - t) / 2
+    gens = max(1, min(max_gens, int(budget_s / max(per_gen, 1e-6)) - 1))
     cfg = gao.Config(m=m, n=n, seed=seed, fitness=kind, max_generations=gens,
                      stop_on_found=False)
     t = time.perf_counter()
     gao.run(cfg)
     dt = time.perf_counter() - t
-    return {"value": n * (gens + 1) / dt, "unit": "evals/s", "cores": gao.num_threads(),
-            "kind": "oracle",
+    return n * (gens + 1) / dt, gens, dt
+
+
+def cpu_baseline(m, n, seed, kind, budget_s=15.0):
+    """The oracle (plain C, OpenMP over individuals) on a bounded sample of
+    the same workload, with every host thread and with one: init, fitness
+    and as many generations as fit in about budget_s seconds (half that for
+    the single thread)."""
+    from oracle import gao
+    threads = gao.num_threads()
+    rate, gens, dt = oracle_rate(m, n, seed, kind, budget_s)
+    gao.set_num_threads(1)
+    try:
+        rate1, gens1, dt1 = oracle_rate(m, n, seed, kind, budget_s / 2)
+    finally:
+        gao.set_num_threads(threads)
+    return {"value": rate, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"m={m}, n={n}, seed {seed}: init + fitness + {gens} generations "
-                      f"({dt:.1f} s)"}
+                      f"({dt:.1f} s)",
+            "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "single_thread": {"value": rate1, "unit": "evals/s", "cores": 1,
+                              "sample": f"init + fitness + {gens1} generations ({dt1:.1f} s)"}}
 
 
 def time_to_solve(runs=32):
@@ -230,6 +262,9 @@ def gram_fitness_metric(reps=1000, repeats=5):
     return {"kernel": "fitness_repeat_kernel<20, SQ>", "bound": "alu",
             "workload": f"m=20, n=40000, seed-1 initial population, SQ key, {reps} evaluations "
                         "of the whole population in one launch",
+            "note": "a ceiling of the Gram + fitness core alone: the 3.2 MB population stays "
+                    "in cache across the repeats; on the per-generation path this work is "
+                    "fused into the children kernel, whose fraction is the roofline above",
             "median_ms": ms, "evals_per_s": evals, "achieved": tops, "peak": peak,
             "unit": "TOP/s", "frac": tops / peak,
             "frac_of_simple_op_peak": tops / SIMPLE_OP_TOPS}
@@ -330,79 +365,91 @@ def bench_default(args):
     out["time_to_solve"] = time_to_solve()
     out["gram_fitness_kernel"] = gram_fitness_metric()
     out["elite_run"] = elite_run_metric()
+    if not args.no_multi:
+        out["batched"] = batched_leg(steps=2)
+        print("default: batched leg done", file=sys.stderr, flush=True)
+        out["served"] = served_leg(args.requests, args.saturated)
     return out
 
 
-def workload_batched(meta_seed=4, count=24):
-    """24 runs: orders from {12,16,20,24,28,36}, sizes uniform in
-    [2000, 60000], seeds meta_seed*10^6 + i, 300 generations each."""
-    import numpy as np
+def config_of(fields):
+    """A library configuration from the workload generator's fields."""
     import paper_2208_14961_amd as ga
-    rng = np.random.default_rng(meta_seed)
-    cfgs = []
-    for i in range(count):
-        m = int(rng.choice([12, 16, 20, 24, 28, 36]))
-        n = int(rng.integers(2000, 60001))
-        cfgs.append(ga.Config(m=m, n=n, seed=meta_seed * 10**6 + i, max_generations=300,
-                              flags=0))
-    return cfgs
+    f = dict(fields)
+    stop = f.pop("stop_on_found")
+    return ga.Config(**f, flags=ga.STOP_ON_FOUND if stop else 0)
 
 
-def bench_batched(args):
+def workload_batched():
+    """24 runs: orders from {12,16,20,24,28,36}, sizes uniform in
+    [2000, 60000], seeds 4*10^6 + i, 300 generations each."""
+    from tests import inputs
+    return [config_of(f) for f in inputs.batched_workload()]
+
+
+def batched_leg(steps=2):
+    """The 24-run batched workload: ga_run_batch (after one warm batch)
+    against the same runs one ga_run each (after a warm pass that allocates
+    their buffers and measures their lanes per child); both sides make the
+    same generations, and their results are compared."""
     import torch
     import paper_2208_14961_amd as ga
     cfgs = workload_batched()
     gens = sum(c.max_generations for c in cfgs)
     evals = sum(c.n * (c.max_generations + 1) for c in cfgs)
-    ga.ga_run_batch(cfgs[:2])  # warm
+    batch = ga.ga_run_batch(cfgs)  # warm
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for _ in range(args.steps):
-        ga.ga_run_batch(cfgs)
+    for _ in range(steps):
+        batch = ga.ga_run_batch(cfgs)
     torch.cuda.synchronize()
-    dt_b = (time.perf_counter() - t) / args.steps
+    dt_b = (time.perf_counter() - t) / steps
     bufs = [buffers(c) for c in cfgs]
-    for c, b in zip(cfgs, bufs):  # warm: the runs measure their lanes per child here
-        ga.ga_run(c, *b)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
     for c, b in zip(cfgs, bufs):
         ga.ga_run(c, *b)
     torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain = [ga.ga_run(c, *b) for c, b in zip(cfgs, bufs)]
+    torch.cuda.synchronize()
     dt_p = time.perf_counter() - t
+    del bufs
+    return {"workload": "24 runs, m in {12,16,20,24,28,36}, n in [2000,60000], 300 generations, "
+                        "seeds 4e6+i",
+            "runs": len(cfgs), "generations": gens,
+            "batched": {"seconds": dt_b, "generations_per_s": gens / dt_b,
+                        "evals_per_s": evals / dt_b, "batches_timed": steps},
+            "plain": {"seconds": dt_p, "generations_per_s": gens / dt_p,
+                      "evals_per_s": evals / dt_p},
+            "speedup_vs_plain": dt_p / dt_b,
+            "results_identical": all(same_result(a, b) for a, b in zip(batch, plain))}
+
+
+def bench_batched(args):
+    leg = batched_leg(steps=max(1, args.steps))
     return {
         "metric": "batched generations/s (24 runs) vs one run per launch",
-        "value": gens / dt_b, "unit": "generations/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": 1, "ms_per_step": 1e3 * dt_b, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "value": leg["batched"]["generations_per_s"], "unit": "generations/s", "n_gpus": 1,
+        "steps": max(1, args.steps), "warmup": 1, "ms_per_step": 1e3 * leg["batched"]["seconds"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
         "config": {"workload": "batched: 24 runs, m in {12..36}, n in [2000,60000], 300 gens"},
-        "evals_per_s": evals / dt_b,
-        "plain": {"generations_per_s": gens / dt_p, "evals_per_s": evals / dt_p,
-                  "seconds": dt_p, "note": "the same runs one ga_run each, buffers allocated "
-                                           "and lanes per child tuned beforehand"},
-        "speedup_vs_plain": dt_p / dt_b,
+        **leg,
     }
 
 
-def workload_served(meta_seed=5, count=2000, rate=50.0):
+def workload_served(count=2000, rate=50.0):
     """Poisson arrivals (mean `rate`/s); order uniform over multiples of 4 in
     [8, 64]; size uniform in [1000, 50000]; 2000-generation budget."""
-    import numpy as np
-    import paper_2208_14961_amd as ga
-    rng = np.random.default_rng(meta_seed)
-    gaps = rng.exponential(1.0 / rate, size=count)
-    arr = np.cumsum(gaps) - gaps[0]
-    cfgs = []
-    for i in range(count):
-        m = int(4 * rng.integers(2, 17))
-        n = int(rng.integers(1000, 50001))
-        cfgs.append(ga.Config(m=m, n=n, seed=meta_seed * 10**6 + i, max_generations=2000))
-    return cfgs, arr
+    from tests import inputs
+    fields, arrivals = inputs.served_workload(count=count, rate=rate)
+    return [config_of(f) for f in fields], arrivals
 
 
-def bench_served(args):
+def served_leg(count, saturated_count):
+    """The served workload: a Poisson stream of `count` requests submitted at
+    their arrival times to a server with a 200 GB budget; then its first
+    `saturated_count` requests at once against one ga_run each."""
     import paper_2208_14961_amd as ga
-    count = args.requests
     cfgs, arrivals = workload_served(count=count)
     srv = ga.Server(hbm_budget_bytes=200 * 10**9)
     t0 = time.perf_counter()
@@ -412,6 +459,9 @@ def bench_served(args):
         if a > now:
             time.sleep(a - now)
         ids.append(srv.submit(c))
+        if len(ids) % 500 == 0:
+            print(f"served: {len(ids)}/{count} requests submitted after "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     results = []
     for k, i in enumerate(ids):
         results.append(srv.wait(i))
@@ -423,20 +473,28 @@ def bench_served(args):
     srv.close()
     solved = [l for l, r in zip(lat, results) if r["found"]]
     evals = sum(c.n * (r["generation"] + 1) for c, r in zip(cfgs, results))
-    saturated = served_saturated(cfgs[:args.saturated]) if args.saturated > 0 else None
+    gens = sum(r["generation"] for r in results)
+    saturated = served_saturated(cfgs[:saturated_count]) if saturated_count > 0 else None
+    return {"workload": f"{count} Poisson requests at 50/s, m in 8..64 step 4, n in "
+                        "[1000,50000], budget 2000 generations, stop on found, 200 GB admission",
+            "requests": count, "seconds": wall, "requests_per_s": count / wall,
+            "generations_per_s": gens / wall, "evals_per_s": evals / wall,
+            "solved": len(solved), "solve_rate": len(solved) / count,
+            "time_to_first_hadamard": {"p50_s": percentile(solved, 50),
+                                       "p99_s": percentile(solved, 99)},
+            "time_to_retire": {"p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99)},
+            "saturated": saturated}
+
+
+def bench_served(args):
+    leg = served_leg(args.requests, args.saturated)
     return {
         "metric": "served search: requests/s and p50/p99 time-to-first-Hadamard",
-        "value": count / wall, "unit": "requests/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "ms_per_step": 1e3 * wall, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": f"served: {count} Poisson requests at 50/s, m in 8..64 step 4, "
-                               "n in [1000,50000], budget 2000 generations, 200 GB admission"},
-        "evals_per_s": evals / wall,
-        "solved": len(solved), "requests": count,
-        "time_to_first_hadamard": {"p50_s": percentile(solved, 50),
-                                   "p99_s": percentile(solved, 99)},
-        "time_to_retire": {"p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99)},
-        "saturated": saturated,
+        "value": leg["requests_per_s"], "unit": "requests/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": 1e3 * leg["seconds"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"served: {leg['workload']}"},
+        **leg,
     }
 
 
@@ -662,6 +720,8 @@ def main():
                          "run one by one (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-multi", action="store_true",
+                    help="default workload: skip the batched and served summaries")
     ap.add_argument("--table2-orders", default="",
                     help="table2: comma-separated orders (default: the table's five)")
     ap.add_argument("--table2-generations", type=int, default=10_000,

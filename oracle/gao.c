@@ -455,3 +455,11 @@ int gao_num_threads(void) {
   return 1;
 #endif
 }
+
+void gao_set_num_threads(int threads) {
+#ifdef _OPENMP
+  if (threads > 0) omp_set_num_threads(threads);
+#else
+  (void)threads;
+#endif
+}

@@ -144,6 +144,8 @@ int gao_run(const gao_config* cfg, int8_t* pop_final, uint32_t* keys_final,
 uint32_t gao_check_invariants(uint32_t m, uint32_t n, const int8_t* pop);
 
 int gao_num_threads(void);
+/* Threads of the OpenMP loops from now on (results do not depend on it). */
+void gao_set_num_threads(int threads);
 
 #ifdef __cplusplus
 }

@@ -125,6 +125,7 @@ def lib():
             "gao_run": (i32, [P(_Config), vp, vp, P(_Result)]),
             "gao_check_invariants": (u32, [u32, u32, vp]),
             "gao_num_threads": (i32, []),
+            "gao_set_num_threads": (None, [i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -262,3 +263,9 @@ def check_invariants(pop: np.ndarray) -> int:
 
 def num_threads() -> int:
     return int(lib().gao_num_threads())
+
+
+def set_num_threads(threads: int) -> None:
+    """Threads of the oracle's loops over individuals (results do not
+    depend on it)."""
+    lib().gao_set_num_threads(int(threads))

@@ -66,3 +66,41 @@ def all_m4_normalized() -> np.ndarray:
         Q[:, 1], Q[:, 2], Q[:, 3] = c1, c2, c3
         out.append(Q)
     return np.stack(out)
+
+
+# --------------------------------------------------------------------------
+# Multi-run workloads: the configurations of the batched and the served
+# benchmark, as plain dicts of configuration fields (m, n, seed,
+# max_generations, stop_on_found); every other field keeps the plain GA's
+# value (binary tournament, crossover 0.5, one pair flip at rate 0.1, SQ).
+# --------------------------------------------------------------------------
+def batched_workload(meta_seed: int = 4, count: int = 24) -> list:
+    """`count` runs: order uniform over {12, 16, 20, 24, 28, 36}, size
+    uniform in [2000, 60000], seed meta_seed * 10^6 + i, 300 generations,
+    no stop on found."""
+    rng = np.random.default_rng(meta_seed)
+    out = []
+    for i in range(count):
+        m = int(rng.choice([12, 16, 20, 24, 28, 36]))
+        n = int(rng.integers(2000, 60001))
+        out.append(dict(m=m, n=n, seed=meta_seed * 10**6 + i, max_generations=300,
+                        stop_on_found=False))
+    return out
+
+
+def served_workload(meta_seed: int = 5, count: int = 2000, rate: float = 50.0):
+    """A Poisson stream of `count` search requests at `rate` per second:
+    (list of config dicts, arrival times in seconds from the first).  Order
+    uniform over the multiples of 4 in [8, 64], size uniform in
+    [1000, 50000], seed meta_seed * 10^6 + i, a budget of 2000 generations,
+    stop at the first Hadamard matrix."""
+    rng = np.random.default_rng(meta_seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(count):
+        m = int(4 * rng.integers(2, 17))
+        n = int(rng.integers(1000, 50001))
+        out.append(dict(m=m, n=n, seed=meta_seed * 10**6 + i, max_generations=2000,
+                        stop_on_found=True))
+    return out, arrivals
