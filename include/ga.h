@@ -219,6 +219,22 @@ ga_status ga_step(const ga_config* cfg, const uint32_t* pop_in,
                   uint32_t* keys_out, uint32_t gen_in, void* stream);
 
 /*
+ * ga_step without device allocation, for callers that cannot allocate
+ * (work under HIP graph capture, serving loops that forbid allocation).
+ * Same arguments, validation and results as ga_step.  Its run state and
+ * selection workspace live in a fixed device array of the library
+ * (288.5 KiB per device, held until the process ends) that covers every
+ * population the library accepts (n <= 2^24; larger n is GA_EINVAL); the
+ * call clears what must start at zero with a kernel of its own, so it
+ * enqueues no memset and no allocation, and can be captured.  Every call on
+ * one device shares that array: calls that overlap on one device (two
+ * streams, or two threads) race and must be ordered by the caller.  Async.
+ */
+ga_status ga_step_static(const ga_config* cfg, const uint32_t* pop_in,
+                         const uint32_t* keys_in, uint32_t* pop_out,
+                         uint32_t* keys_out, uint32_t gen_in, void* stream);
+
+/*
  * A whole run (Sec. 3, the algorithm; Sec. 6 loop): init, fitness, then
  * ga_step until a generation holds a key of 0 (with GA_STOP_ON_FOUND) or
  * max_generations steps were made.  Synchronous: returns when done.

@@ -128,6 +128,7 @@ def lib() -> ctypes.CDLL:
             "ga_fitness_repeat": (i32, [P(_Config), vp, vp, u32, vp]),
             "ga_tuned_lanes": (u32, [P(_Config)]),
             "ga_step": (i32, [P(_Config), vp, vp, vp, vp, u32, vp]),
+            "ga_step_static": (i32, [P(_Config), vp, vp, vp, vp, u32, vp]),
             "ga_run": (i32, [P(_Config), vp, vp, vp, vp, P(_Result), vp]),
             "ga_run_batch": (i32, [P(_Config), u32, P(_Result), vp]),
             "ga_check_invariants": (i32, [P(_Config), vp, P(u32), vp]),
@@ -219,6 +220,15 @@ def ga_step(cfg: Config, pop_in, keys_in, pop_out, keys_out, gen_in: int,
     _check(lib().ga_step(ctypes.byref(cfg.c()), _dev(pop_in, sh, "pop_in"),
                          _dev(keys_in, (cfg.n,), "keys_in"), _dev(pop_out, sh, "pop_out"),
                          _dev(keys_out, (cfg.n,), "keys_out"), gen_in, _stream(stream)))
+
+
+def ga_step_static(cfg: Config, pop_in, keys_in, pop_out, keys_out, gen_in: int,
+                   stream=None) -> None:
+    """ga_step on the library's fixed device workspace: no allocation."""
+    sh = pop_shape(cfg)
+    _check(lib().ga_step_static(ctypes.byref(cfg.c()), _dev(pop_in, sh, "pop_in"),
+                                _dev(keys_in, (cfg.n,), "keys_in"), _dev(pop_out, sh, "pop_out"),
+                                _dev(keys_out, (cfg.n,), "keys_out"), gen_in, _stream(stream)))
 
 
 def ga_run(cfg: Config, pop_a, pop_b, keys_a, keys_b, stream=None) -> dict:
