@@ -19,6 +19,8 @@ the same 24 runs one after another.
 then the first requests of the stream submitted at once against the same
 requests run one ga_run after another.
 --workload pmc: a short run for hardware-counter passes (no timing).
+--workload elite: the elitist plain GA (m = 32, n = 200,000, 2,000 elites,
+1,000 generations) alone.
 --workload long_runs: the paper's single runs to a first Hadamard matrix
 (Sec. 4.4) with its population sizes and mutation counts.
 --workload table2: the paper's timing table (10^4 generations of 40,000
@@ -288,6 +290,26 @@ def elite_run_metric():
             "seconds": dt, "generations_per_s": cfg.max_generations / dt,
             "evals_per_s": (cfg.n - cfg.elite) * cfg.max_generations / dt,
             "best_key": r["best_key"]}
+
+
+def bench_elite(args):
+    """The elitist run alone, `--steps` timed runs after a warm one."""
+    import torch
+    import paper_2208_14961_amd as ga
+    cfg = ga.Config(m=32, n=200000, seed=2, fitness=ga.FIT_SQ_PLUS_NNZ, elite=2000,
+                    max_generations=1000, flags=0)
+    bufs = buffers(cfg)
+    ga.ga_run(cfg, *bufs)
+    dt = timed_runs(cfg, bufs, max(1, args.steps)) / max(1, args.steps)
+    gens = cfg.max_generations
+    return {"metric": "elitist plain GA generations/s", "value": gens / dt,
+            "unit": "generations/s", "n_gpus": 1, "steps": max(1, args.steps), "warmup": 1,
+            "ms_per_step": 1e3 * dt, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "plain GA m=32 n=200000 seed 2, SQ+NNZ, elite 2000, "
+                                   "1000 generations"},
+            "evals_per_s": (cfg.n - cfg.elite) * gens / dt, "us_per_generation": 1e6 * dt / gens,
+            "lanes_per_child": ga.ga_tuned_lanes(cfg)}
 
 
 def bench_default(args):
@@ -713,7 +735,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="default",
-                    choices=["default", "batched", "served", "pmc", "paper_study", "table2", "long_runs"])
+                    choices=["default", "batched", "served", "pmc", "elite", "paper_study", "table2",
+                             "long_runs"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--saturated", type=int, default=200,
                     help="served: requests of the stream also submitted at once and "
@@ -746,7 +769,7 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     fn = {"default": bench_default, "batched": bench_batched, "served": bench_served,
-          "pmc": workload_pmc, "paper_study": bench_paper_study,
+          "pmc": workload_pmc, "elite": bench_elite, "paper_study": bench_paper_study,
           "table2": bench_table2, "long_runs": bench_long_runs}
     out = fn[args.workload](args)
     print(json.dumps(out), flush=True)

@@ -123,6 +123,12 @@ struct Workspace {
   hipEvent_t ev_t[2] = {nullptr, nullptr};  // timing of tuning chunks
   uint32_t* perm = nullptr;        // paper mode: a chunk's slot table
   uint64_t perm_cap = 0;           // its entries
+  // elitism: the next elites' sources, the candidate bitmap and the
+  // selection's item list, for populations up to elite_cap
+  EliteWork* ew = nullptr;
+  uint32_t* emark = nullptr;
+  uint32_t* eitems = nullptr;      // slots of long candidate lists: elite_cap words
+  uint64_t elite_cap = 0;
   // cached graph of one chunk of generations, valid for `graph_key`
   hipGraphExec_t graph = nullptr;
   std::vector<char> graph_key;
@@ -255,10 +261,17 @@ static uint32_t select_count(const ga_config* c) {
 
 // Enqueues launch `node` of a chunk for a single population: the
 // selection kernels if the mode needs them, then the children kernel.
-// slots: paper mode's slot table row for this launch, or null.
+// slots: paper mode's slot table row for this launch, or null.  With the
+// elitism of ga_run (d.ew set) the children launch copies the elites chosen
+// before it and one launch after it chooses the next generation's.
 static ga_status enqueue_generation(const ga_config* c, const PopDesc& d,
                                     Workspace* w, uint32_t node,
                                     const uint32_t* slots, hipStream_t s) {
+  if (d.ew) {
+    GA_TRY(launch_children_one(d, node, s), "children kernel");
+    GA_TRY(launch_elite_select(d, node + 1, w->eitems, s), "elite selection kernel");
+    return GA_OK;
+  }
   const uint32_t cnt = select_count(c);
   if (cnt > 0)
     GA_TRY(launch_select(d, cnt, w->sel, node, slots, s), "selection kernels");
@@ -439,6 +452,30 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     GA_TRY(hipMalloc(&w->perm, (size_t)D * chunk * sizeof(uint32_t)), "hipMalloc(slot table)");
     w->perm_cap = (uint64_t)D * chunk;
   }
+  // Elitism: the elites come from a short candidate list each generation
+  // (EliteWork), on buffers sized for the population.
+  const bool elites = cfg->selection == GA_SEL_TOURNAMENT && cfg->elite > 0 && nchunks > 0;
+  if (elites && w->elite_cap < cfg->n) {
+    GA_TRY(hipStreamSynchronize(w->capture), "hipStreamSynchronize");
+    if (w->graph) {
+      GA_TRY(hipGraphExecDestroy(w->graph), "hipGraphExecDestroy");
+      w->graph = nullptr;
+    }
+    if (w->emark) GA_TRY(hipFree(w->emark), "hipFree(candidate bitmap)");
+    if (w->eitems) GA_TRY(hipFree(w->eitems), "hipFree(candidate list)");
+    w->emark = nullptr;
+    w->eitems = nullptr;
+    w->elite_cap = 0;
+    if (!w->ew) GA_TRY(hipMalloc(&w->ew, sizeof(EliteWork)), "hipMalloc(elites)");
+    GA_TRY(hipMalloc(&w->emark, ((size_t)cfg->n + 31) / 32 * sizeof(uint32_t)),
+           "hipMalloc(candidate bitmap)");
+    GA_TRY(hipMalloc(&w->eitems, (size_t)cfg->n * sizeof(uint32_t)), "hipMalloc(candidate list)");
+    w->elite_cap = cfg->n;
+  }
+  if (elites) {
+    d.ew = w->ew;
+    d.mark = w->emark;
+  }
   auto capture = [&](const PopDesc& dd) -> ga_status {
     std::vector<char> key(sizeof(PopDesc) + sizeof(ga_config) + sizeof(uint32_t*));
     uint32_t* tab = table ? w->perm : nullptr;
@@ -485,6 +522,16 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     // the capture stream starts after the work already enqueued on s
     GA_TRY(hipEventRecord(w->ev[2], s), "hipEventRecord");
     GA_TRY(hipStreamWaitEvent(w->capture, w->ev[2], 0), "hipStreamWaitEvent");
+    // the first generation's elites, from the whole initial population, and
+    // a clear candidate bitmap
+    if (elites) {
+      GA_TRY(hipMemsetAsync(w->emark, 0, ((size_t)cfg->n + 31) / 32 * sizeof(uint32_t),
+                            w->capture),
+             "hipMemsetAsync(candidate bitmap)");
+      GA_TRY(launch_select(d, cfg->elite, w->sel, 0, nullptr, w->capture, w->ew->src,
+                           &w->ew->kstar),
+             "selection kernels");
+    }
   }
   if (explore) {
     float best_ms = 0;

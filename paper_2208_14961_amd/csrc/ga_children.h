@@ -455,7 +455,56 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d,
                   make_uint4(f[4 * s], f[4 * s + 1], f[4 * s + 2], f[4 * s + 3]));
   }
   if (l == 0) store_key<NT>(kout + dst, key);
+  // elitism in ga_run: a child below the largest elite key may be among the
+  // next elites (rare: one atomic per such child)
+  if (d.mark && l == 0 && key < d.ew->kstar) atomicOr(&d.mark[dst >> 5], 1u << (dst & 31u));
   return ((unsigned long long)key << 32) | dst;
+}
+
+// Elitism in ga_run: block b copies elites b, b + nblocks, ... of generation
+// G (rows ew->src[s] of G - 1, with their keys) into slots s.  The block's
+// first elite is loaded before its child is made (load_first_elite) and
+// stored after (copy_elites), so the copy adds no round trip of its own.
+struct EliteRow {
+  uint4 v;       // this lane's 16-byte group of the row (lanes < V)
+  uint32_t key;  // its key (lane 0)
+};
+template <int M>
+__device__ __forceinline__ EliteRow load_first_elite(const PopDesc& d, uint32_t G) {
+  constexpr uint32_t V = M * col_words(M) / 4;  // 16-byte groups per row
+  EliteRow r{make_uint4(0, 0, 0, 0), 0u};
+  const uint32_t s = blockIdx.x - d.block_begin;
+  if (s >= d.elite) return r;
+  const bool odd_in = ((G - 1) & 1u) != 0;
+  const uint4* pin = reinterpret_cast<const uint4*>(odd_in ? d.pop_b : d.pop_a);
+  const uint32_t* kin = odd_in ? d.keys_b : d.keys_a;
+  const uint32_t src = d.ew->src[s];
+  if (threadIdx.x < V) r.v = pin[(size_t)src * V + threadIdx.x];
+  if (threadIdx.x == 0) r.key = kin[src];
+  return r;
+}
+template <int M, bool NT>
+__device__ __forceinline__ void copy_elites(const PopDesc& d, uint32_t G, const EliteRow& first) {
+  constexpr uint32_t V = M * col_words(M) / 4;
+  const bool odd_in = ((G - 1) & 1u) != 0;
+  const uint4* pin = reinterpret_cast<const uint4*>(odd_in ? d.pop_b : d.pop_a);
+  const uint32_t* kin = odd_in ? d.keys_b : d.keys_a;
+  uint4* pout = reinterpret_cast<uint4*>(odd_in ? d.pop_a : d.pop_b);
+  uint32_t* kout = odd_in ? d.keys_a : d.keys_b;
+  uint32_t s = blockIdx.x - d.block_begin;
+  if (s >= d.elite) return;
+  if (threadIdx.x < V) store_row<NT>(pout + (size_t)s * V + threadIdx.x, first.v);
+  if (threadIdx.x == 0) store_key<NT>(kout + s, first.key);
+  for (uint32_t v = kChildBlock + threadIdx.x; v < V; v += kChildBlock) {
+    const uint32_t src = d.ew->src[s];
+    store_row<NT>(pout + (size_t)s * V + v, pin[(size_t)src * V + v]);
+  }
+  for (s += d.nblocks; s < d.elite; s += d.nblocks) {
+    const uint32_t src = d.ew->src[s];
+    for (uint32_t v = threadIdx.x; v < V; v += kChildBlock)
+      store_row<NT>(pout + (size_t)s * V + v, pin[(size_t)src * V + v]);
+    if (threadIdx.x == 0) store_key<NT>(kout + s, kin[src]);
+  }
 }
 
 // Generation G of launch `node`, and whether it runs (see RunState).  The
@@ -487,7 +536,11 @@ __global__ __launch_bounds__(kChildBlock) void children_one_kernel(PopDesc d,
   using Q = Lanes<M, L>;
   __shared__ __align__(16) uint32_t lds[Q::CPB * M * Q::W];
   children_block(d, node, [&](uint32_t G) __attribute__((always_inline)) {
-    return child<M, NEED, L, true>(d, G, lds);
+    EliteRow er{make_uint4(0, 0, 0, 0), 0u};
+    if (d.ew) er = load_first_elite<M>(d, G);
+    const unsigned long long b = child<M, NEED, L, true>(d, G, lds);
+    if (d.ew) copy_elites<M, true>(d, G, er);
+    return b;
   });
 }
 

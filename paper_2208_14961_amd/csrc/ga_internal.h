@@ -67,6 +67,20 @@ inline bool run_done(const RunState& s, uint32_t max_gen, bool stop_on_found) {
 // One population in a step launch.
 struct SelWork;
 
+// Elitism inside ga_run.  Generation G's elites are the e smallest (key,
+// slot) of generation G - 1, in slots 0 .. e-1 of G, so they precede every
+// child on ties: the e smallest of G are among those elites and the
+// children whose key is below kstar, the largest elite key.  The children
+// launch of G copies the elites (src) and marks such children in a bitmap;
+// one single-block launch then picks the next elites from that short list.
+struct EliteWork {
+  uint32_t kstar;            // largest key among the elites of the generation
+                             // the next children launch makes
+  uint32_t pad[63];
+  uint32_t src[kMaxElite];   // elite s of that generation is row src[s] of
+                             // the one before (increasing)
+};
+
 struct PopDesc {
   uint32_t* pop_a;
   uint32_t* pop_b;
@@ -92,6 +106,9 @@ struct PopDesc {
                          // selection workspace (null otherwise)
   uint32_t* slots;       // batched and served paper-mode runs: kBatchTableRows rows of
                          // slot permutations for a chunk (null: walked inline)
+  EliteWork* ew;         // ga_run with elitism: the children launch copies the elites
+                         // and marks candidates (null: elites copied by the selection)
+  uint32_t* mark;        // with ew: bitmap over slots, a child below ew->kstar
 };
 
 // Workspace of the selection pipeline of one population.
@@ -120,12 +137,21 @@ hipError_t launch_fitness_repeat(const ga_config* c, const uint32_t* pop,
 // pi^-1(rank)), G from the state and the launch's node.  slots: paper mode's
 // pi^-1 for this launch's generation from launch_perm_table, or null to
 // evaluate it inline.
+// src_out, kstar_out (elitism in ga_run): write the sources of the selected
+// ranks and the threshold key there instead of copying the rows.
 hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
-                         uint32_t node, const uint32_t* slots, hipStream_t s);
+                         uint32_t node, const uint32_t* slots, hipStream_t s,
+                         uint32_t* src_out = nullptr, uint32_t* kstar_out = nullptr);
 // paper mode: pi^-1 over [0, count) for the generations of launches
 // 0 .. nodes-1 of a chunk, row by row into out[nodes][count]
 hipError_t launch_perm_table(const PopDesc& d, uint32_t count, uint32_t nodes,
                              uint32_t* out, hipStream_t s);
+// ga_run with elitism: the elites of generation gen_base + node + 1 of d
+// chosen from generation gen_base + node (see EliteWork), from its elites
+// and its marked children.  item_slot: n entries of scratch.  (The first
+// generation's come from launch_select with src_out.)
+hipError_t launch_elite_select(const PopDesc& d, uint32_t node, uint32_t* item_slot,
+                               hipStream_t s);
 // children of every population in descs (device array), all of order m
 hipError_t launch_children(const PopDesc* descs_dev, const uint32_t* block_pop,
                            uint32_t total_blocks, uint32_t m, uint32_t lanes,

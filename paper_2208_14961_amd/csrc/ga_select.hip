@@ -30,6 +30,8 @@ struct SelArgs {
   uint32_t n, count, mw, paper;
   uint32_t node, max_gen, stop_on_found;
   uint32_t one_level;  // every key < 4096: the high digit is 0, no first pass
+  uint32_t* src_out;    // elitism in ga_run: the scatter writes the selected
+  uint32_t* kstar_out;  // sources (src_out[rank]) and T, and copies no rows
 };
 
 // Generation G produced by this launch and whether it runs (see RunState);
@@ -377,6 +379,13 @@ __global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a, uint32_t fused,
   }
   uint32_t total;
   uint32_t at = block_exclusive_scan(mine, &total);
+  if (a.src_out) {  // the sources of the elites only
+#pragma unroll
+    for (int e = 0; e < PER; ++e)
+      if (slots[e] != ~0u) a.src_out[slots[e]] = i0 + e;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.kstar_out = T;
+    return;
+  }
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
     if (slots[e] != ~0u) {
@@ -413,8 +422,11 @@ __global__ __launch_bounds__(kBlock) void sel_scatter(SelArgs a, uint32_t fused,
 }
 
 hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
-                         uint32_t node, const uint32_t* slots, hipStream_t s) {
+                         uint32_t node, const uint32_t* slots, hipStream_t s,
+                         uint32_t* src_out, uint32_t* kstar_out) {
   SelArgs a;
+  a.src_out = src_out;
+  a.kstar_out = kstar_out;
   a.slots = slots;
   a.pop_a = d.pop_a;
   a.pop_b = d.pop_b;

@@ -365,6 +365,28 @@ def test_run_parity(cfg):
     _same_run(cfg)
 
 
+@pytest.mark.parametrize("cfg", [
+    # keys 0, 16 and 48 only: ties everywhere, the elites' threshold among them
+    ga.Config(m=4, n=1000, seed=1, elite=300, max_generations=40, flags=0),
+    # almost every slot an elite: five child pairs, more elites than blocks
+    ga.Config(m=8, n=600, seed=2, elite=590, max_generations=30, flags=0),
+    ga.Config(m=12, n=5000, seed=3, elite=1, fitness=ga.FIT_NNZ, max_generations=100),
+    ga.Config(m=20, n=3001, seed=4, elite=700, fitness=ga.FIT_ABS, max_generations=70, flags=0),
+    ga.Config(m=32, n=20000, seed=5, elite=200, fitness=ga.FIT_SQ_PLUS_NNZ, max_generations=70,
+              flags=0),
+    ga.Config(m=44, n=2000, seed=6, elite=31, fitness=ga.FIT_F1, max_generations=66, flags=0),
+    ga.Config(m=68, n=900, seed=7, elite=90, fitness=ga.FIT_F2, max_generations=20, flags=0),
+    ga.Config(m=100, n=500, seed=8, elite=65, fitness=ga.FIT_ABS, max_generations=10, flags=0),
+])
+def test_run_elitism(cfg):
+    """Whole elitist runs through ga_run, whose elites come from the previous
+    elites and the children below their largest key: equal to the oracle's
+    runs, which rank the whole population."""
+    torch_cuda()
+    announce("run elitism", cfg)
+    _same_run(cfg)
+
+
 @pytest.mark.parametrize("m,nc,nr,kind,gens", [
     (12, 1, 1, ga.FIT_F1, 400), (12, 4, 4, ga.FIT_F2, 150), (16, 1, 4, ga.FIT_F2, 150),
     (16, 3, 2, ga.FIT_F1, 100),
@@ -615,3 +637,200 @@ def test_invalid_configs_rejected():
     with pytest.raises(ga.GAError) as e:  # one invalid run rejects the batch
         ga.ga_run_batch([ga.Config(m=8, n=100, elite=2), ga.Config(m=18, n=100)])
     assert e.value.status == ga.GA_EINVAL
+
+
+# --------------------------------------------------------------------------
+# Whole runs of the benchmarked configurations, through the timed entry
+# points (ga_run's captured chunks and in-run lane measurement, the batched
+# launches, the server), against the oracle's whole runs
+# --------------------------------------------------------------------------
+import hashlib  # noqa: E402
+import json  # noqa: E402
+import os  # noqa: E402
+
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    """Stored oracle results, written by tests/golden/make_golden.py (which
+    calls only the oracle)."""
+    with open(os.path.join(GOLDEN_DIR, name)) as f:
+        return json.load(f)
+
+
+def _digest(a) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def _rows(Q) -> list:
+    return ["".join("+" if x > 0 else "-" for x in row) for row in Q]
+
+
+def _equals_record(got, rec):
+    for k in ("found", "generation", "index", "best_key"):
+        assert got[k] == rec[k], (k, got[k], rec[k], rec["config"])
+    assert _rows(got["matrix"]) == rec["matrix"], rec["config"]
+
+
+def _from_fields(f) -> ga.Config:
+    f = dict(f)
+    stop = f.pop("stop_on_found")
+    return ga.Config(**f, flags=ga.STOP_ON_FOUND if stop else 0)
+
+
+@pytest.mark.parametrize("kind", [ga.FIT_SQ, ga.FIT_ABS])
+def test_full_size_m20_n40000_whole_run(kind):
+    """The benchmark's timed path at full size: ga_run at m = 20, n = 40,000,
+    seed 1, 500 generations, no stop on found, SQ and ABS keys.  The first
+    call measures the lanes per child on its own chunks, the second reuses
+    the measured choice (as the timed benchmark steps do); both leave the
+    oracle's final population and keys and report its result."""
+    torch_cuda()
+    cfg = ga.Config(m=20, n=40000, seed=1, fitness=kind, max_generations=500, flags=0)
+    announce("whole run m20 n40000", kind)
+    want, opop, okeys = gao.run(to_oracle(cfg))
+    for call in range(2):
+        res, pop, keys = _run_gpu(cfg)
+        for k in ("found", "generation", "index", "best_key"):
+            assert res[k] == want[k], (call, k, res, want)
+        assert np.array_equal(res["matrix"], opop[want["index"]])
+        assert np.array_equal(keys, okeys), call
+        assert np.array_equal(pop, opop), call
+
+
+def test_full_size_m32_n200000_elite_20_generations():
+    """The elitist configuration (m = 32, n = 200,000, seed 2, SQ + NNZ,
+    2,000 elites) through ga_run for 20 generations: final population, keys
+    and result equal the oracle's run."""
+    torch_cuda()
+    announce("whole run m32 n200000 elite, 20 generations")
+    _same_run(ga.Config(m=32, n=200000, seed=2, fitness=ga.FIT_SQ_PLUS_NNZ, elite=2000,
+                        max_generations=20, flags=0))
+
+
+def test_full_size_m32_n200000_elite_1000_generations():
+    """The same configuration over its whole 1,000-generation budget (the
+    benchmark's elitist run), twice (lane measurement, then the measured
+    choice): result and digests of the final population and keys equal the
+    stored oracle run."""
+    torch_cuda()
+    rec = _golden("elite_m32_n200000.json")["run"]
+    cfg = _from_fields(rec["config"])
+    assert (cfg.m, cfg.n, cfg.elite, cfg.max_generations) == (32, 200000, 2000, 1000)
+    for call in range(2):
+        announce("whole run m32 n200000 elite, 1000 generations", call)
+        res, pop, keys = _run_gpu(cfg)
+        _equals_record(res, rec)
+        assert _digest(keys.astype("<u4")) == rec["keys_sha256"], call
+        assert _digest(pop) == rec["population_sha256"], call
+
+
+def test_batched_workload_24_runs_equal_oracle():
+    """The batched benchmark workload at full size (24 runs, orders 12..36,
+    populations 2,000..60,000, 300 generations): every run of the batched
+    launches reports the stored oracle run's result, and each run alone
+    through ga_run leaves the oracle's final population and keys."""
+    torch_cuda()
+    recs = _golden("batched_24runs.json")["runs"]
+    cfgs = [_from_fields(f) for f in inputs.batched_workload()]
+    assert [r["config"] for r in recs] == inputs.batched_workload()
+    announce("batched workload", len(cfgs))
+    for got, rec in zip(ga.ga_run_batch(cfgs), recs):
+        _equals_record(got, rec)
+    for cfg, rec in zip(cfgs, recs):
+        announce("batched workload run alone", cfg.m, cfg.n, cfg.seed)
+        res, pop, keys = _run_gpu(cfg)
+        _equals_record(res, rec)
+        assert _digest(keys.astype("<u4")) == rec["keys_sha256"]
+        assert _digest(pop) == rec["population_sha256"]
+
+
+def test_served_stream_slice_equals_plain_runs_and_oracle():
+    """The first 200 requests of the served benchmark's stream (orders 8..64,
+    populations 1,000..50,000, 2,000-generation budget, stop on found), all
+    submitted to one server: each result equals the same request's ga_run,
+    and the requests of order <= 16 equal the stored oracle runs."""
+    torch_cuda()
+    gold = _golden("served_slice.json")
+    fields, _ = inputs.served_workload()
+    cfgs = [_from_fields(f) for f in fields[:gold["requests"]]]
+    announce("served slice", len(cfgs))
+    srv = ga.Server(hbm_budget_bytes=200 * 10**9)
+    try:
+        ids = [srv.submit(c) for c in cfgs]
+        served = [srv.wait(i) for i in ids]
+    finally:
+        srv.close()
+    by_request = {r["request"]: r for r in gold["runs"]}
+    assert sorted(by_request) == [i for i, c in enumerate(cfgs) if c.m <= gold["max_order"]]
+    for i, rec in by_request.items():
+        assert rec["config"] == fields[i]
+        _equals_record(served[i], rec)
+    cache = {}
+    for i, (cfg, got) in enumerate(zip(cfgs, served)):
+        shape = (cfg.m, cfg.n)
+        if shape not in cache:
+            cache.clear()
+            cache[shape] = (empty_pop(cfg), empty_pop(cfg), empty_keys(cfg), empty_keys(cfg))
+        want = ga.ga_run(cfg, *cache[shape])
+        for k in ("found", "generation", "index", "best_key"):
+            assert got[k] == want[k], (i, k, got[k], want[k])
+        assert np.array_equal(got["matrix"], want["matrix"]), i
+
+
+def _run_bytes(cfg: ga.Config) -> int:
+    """Device bytes of a tournament run without elites on the server: two
+    populations and two key arrays, each rounded up to 256 bytes."""
+    pop = cfg.n * cfg.m * cfg.words * 4
+    return 2 * ((pop + 255) // 256 * 256) + 2 * ((cfg.n * 4 + 255) // 256 * 256)
+
+
+def test_server_small_request_passes_a_waiting_large_one():
+    """A request that does not fit the budget beside a running one waits,
+    while a later small request that fits is admitted and finishes first;
+    the large one runs once memory frees up.  Every result equals the
+    oracle's."""
+    torch_cuda()
+    long_run = ga.Config(m=8, n=2000, seed=21, max_generations=2000, flags=0)
+    large = ga.Config(m=8, n=2200, seed=22, max_generations=5, flags=0)
+    small = ga.Config(m=8, n=200, seed=23, max_generations=5, flags=0)
+    budget = max(_run_bytes(large), _run_bytes(long_run) + _run_bytes(small)) + 1024
+    assert _run_bytes(large) + _run_bytes(long_run) > budget
+    announce("server bypass", budget)
+    srv = ga.Server(hbm_budget_bytes=budget)
+    try:
+        ids = [srv.submit(c) for c in (long_run, large, small)]
+        res = [srv.wait(i) for i in ids]
+        lat = [srv.latency(i) for i in ids]
+    finally:
+        srv.close()
+    assert lat[2] < lat[0] < lat[1], lat
+    for cfg, got in zip((long_run, large, small), res):
+        _equals_oracle_run(cfg, got)
+
+
+def test_server_stop_fails_unfinished_and_refuses_submissions():
+    """ga_server_stop ends the worker: a finished result stays readable, the
+    requests still queued or running fail with GA_ESTOPPED, and a later
+    submission is refused with the same status."""
+    torch_cuda()
+    quick = ga.Config(m=8, n=256, seed=1, max_generations=100)
+    slow = ga.Config(m=36, n=20000, seed=5, max_generations=1_000_000, flags=0)
+    announce("server stop")
+    srv = ga.Server(hbm_budget_bytes=1 << 30)
+    try:
+        q = srv.submit(quick)
+        done = srv.wait(q)
+        ids = [srv.submit(ga.Config(**{**slow.__dict__, "seed": s})) for s in range(3)]
+        srv.stop()
+        for i in ids:
+            with pytest.raises(ga.GAError) as e:
+                srv.wait(i)
+            assert e.value.status == ga.GA_ESTOPPED
+        with pytest.raises(ga.GAError) as e:
+            srv.submit(quick)
+        assert e.value.status == ga.GA_ESTOPPED
+        assert srv.wait(q)["best_key"] == done["best_key"]
+        _equals_oracle_run(quick, done)
+    finally:
+        srv.close()
