@@ -232,8 +232,24 @@ __global__ __launch_bounds__(kBlock) void finish_kernel(
   finish_run(descs[blockIdx.x]);
 }
 
+// The same for one run over several blocks: each block's smallest (key,
+// slot) meets the others in one 64-bit atomic minimum (the state's best is
+// ~0 from the run's start).
 __global__ __launch_bounds__(kBlock) void finish_one_kernel(PopDesc d) {
-  finish_run(d);
+  RunState* st = d.state;
+  const uint32_t found = st->found_gen;
+  const uint32_t g = (d.stop_on_found && found <= d.max_gen) ? found : d.max_gen;
+  const uint32_t* keys = (g & 1u) ? d.keys_b : d.keys_a;
+  unsigned long long best = ~0ull;
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < d.n; i += gridDim.x * kBlock) {
+    const unsigned long long v = ((unsigned long long)keys[i] << 32) | i;
+    best = v < best ? v : best;
+  }
+  best = block_min_u64(best);
+  if (threadIdx.x == 0) {
+    atomicMin(&st->best, best);
+    if (blockIdx.x == 0) st->final_gen = g;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -465,7 +481,9 @@ hipError_t launch_finish(const PopDesc* descs_dev, uint32_t ndesc,
 }
 
 hipError_t launch_finish_one(const PopDesc& d, hipStream_t s) {
-  hipLaunchKernelGGL(finish_one_kernel, dim3(1), dim3(kBlock), 0, s, d);
+  // about eight keys per thread, at most 512 blocks
+  const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(512, cdiv(d.n, 8 * kBlock)));
+  hipLaunchKernelGGL(finish_one_kernel, dim3(blocks), dim3(kBlock), 0, s, d);
   return hipGetLastError();
 }
 
