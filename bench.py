@@ -21,6 +21,8 @@ requests run one ga_run after another.
 --workload pmc: a short run for hardware-counter passes (no timing).
 --workload elite: the elitist plain GA (m = 32, n = 200,000, 2,000 elites,
 1,000 generations) alone.
+--workload gram: the Gram + fitness kernel (ga_fitness_repeat) on the packed
+popcount path and on the int8 matrix cores, per order.
 --workload long_runs: the paper's single runs to a first Hadamard matrix
 (Sec. 4.4) with its population sizes and mutation counts.
 --workload table2: the paper's timing table (10^4 generations of 40,000
@@ -77,6 +79,7 @@ def ops_per_eval(m: int, kind: int) -> int:
 
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+INT8_MFMA_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix cores, published (2 ops per MAC)
 
 
 def child_bytes(m: int, t: int = 2):
@@ -310,6 +313,71 @@ def bench_elite(args):
                                    "1000 generations"},
             "evals_per_s": (cfg.n - cfg.elite) * gens / dt, "us_per_generation": 1e6 * dt / gens,
             "lanes_per_child": ga.ga_tuned_lanes(cfg)}
+
+
+def time_repeat(cfg, pop, keys, reps, repeats=5):
+    """Median milliseconds of one ga_fitness_repeat launch (HIP events on the
+    launch's stream), after a warm launch."""
+    import torch
+    import paper_2208_14961_amd as ga
+    ga.ga_fitness_repeat(cfg, pop, keys, reps)
+    s = torch.cuda.current_stream()
+    times = []
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        ga.ga_fitness_repeat(cfg, pop, keys, reps)
+        e1.record(s)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return percentile(times, 50)
+
+
+def bench_gram(args):
+    """Gram + fitness of a whole population evaluated many times in one
+    launch, on the packed popcount path and on the int8 matrix cores, for
+    orders 36..128 (SQ key, n = 40,000 initial population, seed 1).  The
+    popcount path is measured against its instruction-mix peak, the matrix
+    cores against the dense int8 peak with m * P algorithmic multiply-adds
+    per evaluation (the tile padding and the lower triangle are waste)."""
+    import torch
+    import paper_2208_14961_amd as ga
+    orders = [int(x) for x in args.gram_orders.split(",")]
+    n, rows = 40000, []
+    for m in orders:
+        base = ga.Config(m=m, n=n, seed=1, fitness=ga.FIT_SQ)
+        pop, _, keys, _ = buffers(base)
+        ga.ga_init_population(base, pop)
+        pairs = (m - 1) * (m - 2) // 2
+        row = {"m": m, "n": n}
+        for name, flag in (("packed", ga.GRAM_PACKED), ("mfma", ga.GRAM_MFMA)):
+            cfg = ga.Config(m=m, n=n, seed=1, fitness=ga.FIT_SQ, flags=flag)
+            probe = time_repeat(cfg, pop, keys, 4, repeats=1)
+            reps = max(4, int(4 * 2.0 / max(probe, 1e-3)))  # about 2 ms per launch
+            ms = time_repeat(cfg, pop, keys, reps)
+            evals = n * reps / (ms * 1e-3)
+            if name == "packed":
+                tops = evals * ops_per_eval(m, ga.FIT_SQ) / 1e12
+                row[name] = {"evals_per_s": evals, "ms": ms, "reps": reps, "achieved": tops,
+                             "peak": alu_peak_tops(m, ga.FIT_SQ), "unit": "TOP/s",
+                             "frac": tops / alu_peak_tops(m, ga.FIT_SQ)}
+            else:
+                tops = evals * 2 * m * pairs / 1e12
+                row[name] = {"evals_per_s": evals, "ms": ms, "reps": reps, "achieved": tops,
+                             "peak": INT8_MFMA_PEAK_TOPS, "unit": "TOP/s (int8, 2 per MAC)",
+                             "frac": tops / INT8_MFMA_PEAK_TOPS}
+        row["mfma_over_packed"] = row["mfma"]["evals_per_s"] / row["packed"]["evals_per_s"]
+        rows.append(row)
+        print(f"gram: m={m}: packed {row['packed']['evals_per_s']:.3e}/s, mfma "
+              f"{row['mfma']['evals_per_s']:.3e}/s ({row['mfma_over_packed']:.2f}x)",
+              file=sys.stderr, flush=True)
+        del pop, keys
+    return {"metric": "Gram + fitness evaluations/s, packed popcount vs int8 matrix cores",
+            "value": None, "unit": "evals/s", "n_gpus": 1, "steps": 5, "warmup": 1,
+            "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32/i8", "data": "synthetic",
+            "config": {"workload": f"ga_fitness_repeat, SQ, n={n}, orders {orders}"},
+            "rows": rows}
 
 
 def bench_default(args):
@@ -735,8 +803,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="default",
-                    choices=["default", "batched", "served", "pmc", "elite", "paper_study", "table2",
-                             "long_runs"])
+                    choices=["default", "batched", "served", "pmc", "elite", "gram", "paper_study",
+                             "table2", "long_runs"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--saturated", type=int, default=200,
                     help="served: requests of the stream also submitted at once and "
@@ -754,6 +822,8 @@ def main():
     ap.add_argument("--long-seeds", type=int, default=1, help="long_runs: runs per order")
     ap.add_argument("--long-budget", type=int, default=2_000_000,
                     help="long_runs: generation budget per run")
+    ap.add_argument("--gram-orders", default="36,48,52,64,68,84,100,116,128",
+                    help="gram: comma-separated orders (36..128)")
     ap.add_argument("--study-n", type=int, default=1000,
                     help="paper_study: N, half the parent count (n = 4N)")
     ap.add_argument("--study-fitness", default="F2", choices=["F1", "F2"],
@@ -769,7 +839,8 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     fn = {"default": bench_default, "batched": bench_batched, "served": bench_served,
-          "pmc": workload_pmc, "elite": bench_elite, "paper_study": bench_paper_study,
+          "pmc": workload_pmc, "elite": bench_elite, "gram": bench_gram,
+          "paper_study": bench_paper_study,
           "table2": bench_table2, "long_runs": bench_long_runs}
     out = fn[args.workload](args)
     print(json.dumps(out), flush=True)

@@ -97,7 +97,17 @@ enum {
    * (orders 36..64: 4 or 8; orders 68..128: 8 or 16).  Results do not
    * depend on it.                                                          */
   GA_LANES_SHIFT = 8u,
-  GA_LANES_MASK = 0x1F00u
+  GA_LANES_MASK = 0x1F00u,
+  /* How ga_fitness and ga_fitness_repeat form the Gram products (Sec. 3.2),
+   * bits 13..14 of flags: 0 lets the library's table choose per order,
+   * GA_GRAM_PACKED forces xor + popcount on the packed columns, GA_GRAM_MFMA
+   * the int8 matrix-core path (orders 36..128 only: G_ij = 4 s_ij - m with
+   * s = X^T X over the 0/1 indicator X of the -1 entries).  Results do not
+   * depend on it.                                                          */
+  GA_GRAM_SHIFT = 13u,
+  GA_GRAM_MASK = 0x6000u,
+  GA_GRAM_PACKED = 1u << 13,
+  GA_GRAM_MFMA = 2u << 13
 };
 
 enum { GA_MAX_M = 128 };  /* largest order */
@@ -117,7 +127,7 @@ typedef struct {
   uint32_t nr;              /* row pairs per mutated child, <= 64            */
   uint32_t max_generations; /* generation budget of ga_run, < 2^31          */
   uint32_t flags;           /* GA_STOP_ON_FOUND | GA_MUT_SHARED |
-                               lanes << GA_LANES_SHIFT                       */
+                               lanes << GA_LANES_SHIFT | GA_GRAM_*           */
 } ga_config;
 
 typedef struct {

@@ -33,6 +33,11 @@ STOP_ON_FOUND = 1
 MUT_SHARED = 2  # first mutation method of Sec. 3.5: one draw set per generation
 MAX_ORDER = 128  # largest order m the library accepts (GA_MAX_M)
 LANES_SHIFT = 8
+# Gram products of ga_fitness / ga_fitness_repeat: xor + popcount, or the
+# int8 matrix cores (orders 36..128); neither flag: the library's table.
+GRAM_PACKED = 1 << 13
+GRAM_MFMA = 2 << 13
+MFMA_MIN_ORDER = 36
 
 
 def col_words(m: int) -> int:

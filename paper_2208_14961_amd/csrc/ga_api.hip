@@ -76,8 +76,14 @@ ga_status validate(const ga_config* c) {
     set_error("nc=%u nr=%u: need 1..64 when mutation is on", c->nc, c->nr);
     return GA_EINVAL;
   }
-  if (c->flags & ~(uint32_t)(GA_STOP_ON_FOUND | GA_MUT_SHARED | GA_LANES_MASK)) {
+  if (c->flags & ~(uint32_t)(GA_STOP_ON_FOUND | GA_MUT_SHARED | GA_LANES_MASK | GA_GRAM_MASK)) {
     set_error("unknown flags 0x%x", c->flags);
+    return GA_EINVAL;
+  }
+  const uint32_t gram = c->flags & GA_GRAM_MASK;
+  if (gram == GA_GRAM_MASK || (gram == GA_GRAM_MFMA && c->m < kMfmaMinOrder)) {
+    set_error("gram flags 0x%x: GA_GRAM_PACKED, or GA_GRAM_MFMA from order %u", gram,
+              kMfmaMinOrder);
     return GA_EINVAL;
   }
   const uint32_t lanes = (c->flags & GA_LANES_MASK) >> GA_LANES_SHIFT;

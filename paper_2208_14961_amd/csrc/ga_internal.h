@@ -120,6 +120,18 @@ struct SelWork {
   uint32_t bucket, below, T, r;   // results of the radix select
 };
 
+// ---- the Gram products of the standalone fitness ---------------------------
+constexpr uint32_t kMfmaMinOrder = 36;  // the int8 MFMA path: orders 36..128
+// Whether ga_fitness / ga_fitness_repeat use the MFMA path for c: forced by
+// its flags, else the measured choice per order (ga_tuning.hip).
+bool use_mfma(const ga_config* c);
+// Gram + fitness on the matrix cores (ga_mfma.hip): evaluation e < total is
+// individual e mod n; comps and st as in launch_fitness (st only when total
+// is n); a grid sized for `cus` compute units.
+hipError_t launch_fitness_mfma(const ga_config* c, const uint32_t* pop, uint32_t* keys,
+                               uint32_t* comps, RunState* st, uint64_t total, uint32_t cus,
+                               hipStream_t s);
+
 // ---- launchers (ga_kernels.hip, ga_children.hip, ga_select.hip) ---------
 hipError_t launch_init(const ga_config* c, uint32_t* pop, hipStream_t s);
 // keys for all n; comps nullable; st nullable, else a key of 0 in generation

@@ -388,6 +388,8 @@ hipError_t launch_unpack(const ga_config* c, const uint32_t* pop, int8_t* q, hip
 hipError_t launch_fitness(const ga_config* c, const uint32_t* pop,
                           uint32_t* keys, uint32_t* comps, RunState* st,
                           hipStream_t s) {
+  // (the MFMA grid's cap: eight workgroups per CU of the 256 of an MI355X)
+  if (use_mfma(c)) return launch_fitness_mfma(c, pop, keys, comps, st, c->n, 256, s);
   const uint32_t grid = cdiv(c->n, kChildBlock);
   if (c->m > 64) {
     hipLaunchKernelGGL(fitness_kernel_w4, dim3(grid), dim3(kChildBlock), 0, s, pop,
@@ -417,6 +419,7 @@ hipError_t launch_fitness_repeat(const ga_config* c, const uint32_t* pop,
                                  uint32_t* keys, uint32_t reps, uint32_t cus,
                                  hipStream_t s) {
   const uint64_t total = (uint64_t)c->n * reps;
+  if (use_mfma(c)) return launch_fitness_mfma(c, pop, keys, nullptr, nullptr, total, cus, s);
   // eight workgroups of four waves per CU, fewer if the work is smaller
   const uint64_t grid = std::min<uint64_t>((uint64_t)cus * 8, cdiv(total, kBlock));
   if (c->m > 64) {

@@ -46,13 +46,15 @@ def test_population_words():
     dict(flags=ga.lanes_flag(3)), dict(flags=ga.lanes_flag(1)), dict(flags=ga.lanes_flag(16)),
     dict(m=36, flags=ga.lanes_flag(2)), dict(m=68, flags=ga.lanes_flag(4)),
     dict(m=128, flags=ga.lanes_flag(2)), dict(m=64, flags=ga.lanes_flag(16)),
-    dict(m=128, flags=ga.lanes_flag(32)),
+    dict(m=128, flags=ga.lanes_flag(31)),
     # keys that elitism and paper selection cannot rank (the SQ keys reach
     # C(m-1, 2) m^2 >= 2^24 from order 80 on)
     dict(m=80, n=100, elite=1), dict(m=80, n=100, elite=1, fitness=ga.FIT_SQ_PLUS_NNZ),
     dict(m=128, n=400, selection=ga.SEL_PAPER, fitness=ga.FIT_SQ),
     # generation budgets whose generation numbers could pass 2^32
     dict(max_generations=1 << 31), dict(max_generations=(1 << 32) - 1),
+    # the matrix-core Gram path starts at order 36; both Gram flags at once
+    dict(m=32, flags=ga.GRAM_MFMA), dict(m=64, flags=ga.GRAM_MFMA | ga.GRAM_PACKED),
 ])
 def test_invalid_configs(kw):
     base = dict(m=8, n=10)
@@ -80,7 +82,9 @@ def test_valid_configs():
                 ga.Config(m=128, n=100, elite=1, fitness=ga.FIT_ABS),
                 ga.Config(m=100, n=40000, selection=ga.SEL_PAPER, fitness=ga.FIT_F1,
                           xo_threshold=1 << 32, mut_threshold=1 << 32, nc=4, nr=2),
-                ga.Config(m=8, n=10, max_generations=(1 << 31) - 1)]:
+                ga.Config(m=8, n=10, max_generations=(1 << 31) - 1),
+                ga.Config(m=36, n=10, flags=ga.GRAM_MFMA), ga.Config(m=128, n=10, flags=ga.GRAM_MFMA),
+                ga.Config(m=8, n=10, flags=ga.GRAM_PACKED)]:
         assert ga.ga_validate(cfg), cfg
 
 

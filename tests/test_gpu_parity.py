@@ -119,6 +119,62 @@ def test_fitness_all_equal_columns(m):
 
 
 # --------------------------------------------------------------------------
+# Gram products on the matrix cores (int8 MFMA), orders 36..128
+# --------------------------------------------------------------------------
+MFMA_ORDERS = [m for m in ORDERS if m >= ga.MFMA_MIN_ORDER]
+
+
+@pytest.mark.parametrize("m", MFMA_ORDERS)
+def test_fitness_mfma_all_kinds(m):
+    """The matrix-core Gram path gives the oracle's keys and components for
+    every kind, over several waves' worth of individuals and a ragged
+    count, in the single and the repeated form."""
+    torch = torch_cuda()
+    n = 2 * 256 + 37
+    announce("fitness mfma", m, n)
+    pop = inputs.random_population(m, n, seed=1100 + m)
+    dpop = dev_pop_from_int8(pop)
+    for i, kind in enumerate(KINDS):
+        cfg = ga.Config(m=m, n=n, fitness=kind, flags=ga.GRAM_MFMA)
+        keys = empty_keys(cfg)
+        comps = torch.zeros((n, 3), dtype=torch.int32, device="cuda")
+        ga.ga_fitness(cfg, dpop, keys, comps)
+        want, want_c = gao.fitness(to_oracle(cfg), pop, with_comps=True)
+        assert np.array_equal(keys_np(keys), want), kind
+        assert np.array_equal(comps.cpu().numpy().view(np.uint32), want_c)
+        keys2 = empty_keys(cfg)
+        ga.ga_fitness(cfg, dpop, keys2)
+        assert np.array_equal(keys_np(keys2), want), kind
+        keys3 = empty_keys(cfg)
+        ga.ga_fitness_repeat(cfg, dpop, keys3, reps=1 + i % 3)
+        assert np.array_equal(keys_np(keys3), want), kind
+
+
+def test_fitness_mfma_hadamard_and_closed_form():
+    """Hadamard matrices have key 0 on the matrix-core path, and a matrix of
+    equal columns has the closed-form keys (every pair |G| = m)."""
+    torch_cuda()
+    for m in [x for x in hf.ORDERS_WITH_FIXTURE if x >= ga.MFMA_MIN_ORDER]:
+        announce("mfma hadamard", m)
+        pop = inputs.random_population(m, 70, seed=m)
+        pop[33] = hf.hadamard(m)
+        cfg = ga.Config(m=m, n=70, fitness=ga.FIT_F2, flags=ga.GRAM_MFMA)
+        keys = empty_keys(cfg)
+        ga.ga_fitness(cfg, dev_pop_from_int8(pop), keys)
+        k = keys_np(keys)
+        assert k[33] == 0 and np.array_equal(k, gao.fitness(to_oracle(cfg), pop))
+    for m in (36, 64, 68, 100, 128):
+        Q = np.ones((m, m), dtype=np.int8)
+        Q[: m // 2, 1:] = -1
+        P = (m - 1) * (m - 2) // 2
+        for kind, want in [(ga.FIT_SQ, P * m * m), (ga.FIT_ABS, P * m), (ga.FIT_NNZ, P)]:
+            cfg = ga.Config(m=m, n=3, fitness=kind, flags=ga.GRAM_MFMA)
+            keys = empty_keys(cfg)
+            ga.ga_fitness(cfg, dev_pop_from_int8(np.stack([Q] * 3)), keys)
+            assert (keys_np(keys) == want).all(), (m, kind)
+
+
+# --------------------------------------------------------------------------
 # Layout conversion
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("m", [4, 20, 32, 36, 64, 68, 96, 100, 128])
