@@ -10,6 +10,15 @@
 // and reduces d = m/2 - 2 s_ij = -G_ij / 2 over the pairs 1 <= i < j < m
 // into the same (SQ, ABS, NNZ) sums as the popcount path.
 //
+// No entry is masked.  Column 0 and the padding columns are zero, so every
+// entry involving one has s = 0, d = m/2; every diagonal entry of a balanced
+// column has d = -m/2.  Each sum's term f(d) (d^2, |d|, [d != 0]) is the
+// same for both, so the unwanted entries add a known count times f(m/2).
+// The diagonal tiles hold each of their pairs twice (once per triangle):
+// with D and O the sums over diagonal and off-diagonal tiles, the pairs sum
+// to (O - n_off f(m/2)) + (D - n_diag f(m/2)) / 2, the counts coming from
+// the host (mfma_counts).
+//
 // Operands.  For tile t and row step ks, lane l holds the 16 bytes of
 // column c = 16 t + (l mod 16), rows 64 ks + 16 (l / 16) .. + 15: four
 // groups of 4 bits spread into bytes by one 24-bit multiply each.  The same
@@ -71,12 +80,24 @@ __device__ __forceinline__ void mfma_load(const uint32_t* P, uint32_t M, MfmaOps
   }
 }
 
-// This lane's share of the sums over the pairs 1 <= i < j < M.
+// This lane's share of the sums over every entry of the diagonal tiles
+// (*dg) and of the tiles above them (*of).
+template <uint32_t NEED>
+__device__ __forceinline__ void add_tile(const v4i& acc, int H, Sums& s) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int d = H - 2 * acc[r];
+    if (NEED & kNeedSQ) s.sq = acc_sq(s.sq, d);
+    if (NEED & kNeedABS) s.ab = acc_abs(s.ab, (uint32_t)(d + H), (uint32_t)H);
+    if (NEED & kNeedNNZ) s.nz = acc_nz(s.nz, d);
+  }
+}
 template <int T, int KS, uint32_t NEED>
-__device__ __forceinline__ Sums mfma_pair_sums(const MfmaOps<T, KS>& o, uint32_t M) {
-  const uint32_t l = threadIdx.x & 63u, c0 = l & 15u, g = l >> 4;
+__device__ __forceinline__ void mfma_tile_sums(const MfmaOps<T, KS>& o, uint32_t M, Sums* dg,
+                                               Sums* of) {
   const int H = (int)(M / 2);
-  Sums s{0, 0, 0};
+  *dg = Sums{0, 0, 0};
+  *of = Sums{0, 0, 0};
 #pragma unroll
   for (int ti = 0; ti < T; ++ti) {
 #pragma unroll
@@ -85,19 +106,9 @@ __device__ __forceinline__ Sums mfma_pair_sums(const MfmaOps<T, KS>& o, uint32_t
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
         acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(o.op[ti][ks], o.op[tj][ks], acc, 0, 0, 0);
-      const uint32_t j = 16u * tj + c0;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const uint32_t i = 16u * ti + 4u * g + r;
-        const bool valid = i >= 1 && i < j && j < M;
-        const int d = valid ? H - 2 * acc[r] : 0;
-        if (NEED & kNeedSQ) s.sq = acc_sq(s.sq, d);
-        if (NEED & kNeedABS) s.ab = acc_abs(s.ab, (uint32_t)(d + H), (uint32_t)H);
-        if (NEED & kNeedNNZ) s.nz = acc_nz(s.nz, d);
-      }
+      add_tile<NEED>(acc, H, tj == ti ? *dg : *of);
     }
   }
-  return s;
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -106,15 +117,22 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
-// The pair sums of the individual at P, in every lane.
+// The pair sums of the individual at P, in every lane.  n_diag, n_off: the
+// unwanted entries of the diagonal and the off-diagonal tiles.
 template <int T, int KS, uint32_t NEED>
-__device__ __forceinline__ Sums mfma_sums(const uint32_t* P, uint32_t M) {
+__device__ __forceinline__ Sums mfma_sums(const uint32_t* P, uint32_t M, uint32_t n_diag,
+                                          uint32_t n_off) {
   MfmaOps<T, KS> o;
   mfma_load<T, KS>(P, M, o);
-  Sums s = mfma_pair_sums<T, KS, NEED>(o, M);
-  if (NEED & kNeedSQ) s.sq = wave_sum(s.sq);
-  if (NEED & kNeedABS) s.ab = wave_sum(s.ab);
-  if (NEED & kNeedNNZ) s.nz = wave_sum(s.nz);
+  Sums dg, of;
+  mfma_tile_sums<T, KS, NEED>(o, M, &dg, &of);
+  const uint32_t H = M / 2;
+  Sums s{0, 0, 0};
+  if (NEED & kNeedSQ)
+    s.sq = (wave_sum(of.sq) - n_off * H * H) + (wave_sum(dg.sq) - n_diag * H * H) / 2;
+  if (NEED & kNeedABS)
+    s.ab = (wave_sum(of.ab) - n_off * H) + (wave_sum(dg.ab) - n_diag * H) / 2;
+  if (NEED & kNeedNNZ) s.nz = (wave_sum(of.nz) - n_off) + (wave_sum(dg.nz) - n_diag) / 2;
   return s;
 }
 
@@ -124,14 +142,15 @@ __device__ __forceinline__ Sums mfma_sums(const uint32_t* P, uint32_t M) {
 template <int T, int KS, uint32_t NEED>
 __global__ __launch_bounds__(kBlock) void fitness_mfma_kernel(
     const uint32_t* __restrict__ pop, uint32_t n, uint32_t m, uint64_t total, uint32_t kind,
-    uint32_t* __restrict__ keys, uint32_t* __restrict__ comps, RunState* st) {
+    uint32_t n_diag, uint32_t n_off, uint32_t* __restrict__ keys, uint32_t* __restrict__ comps,
+    RunState* st) {
   constexpr uint32_t kWaves = kBlock / 64;
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t stride = (uint64_t)gridDim.x * kWaves;
   const size_t words = (size_t)m * 2 * KS;
   for (uint64_t e = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); e < total; e += stride) {
     const uint32_t k = (uint32_t)(e % n);
-    const Sums s = mfma_sums<T, KS, NEED>(pop + k * words, m);
+    const Sums s = mfma_sums<T, KS, NEED>(pop + k * words, m, n_diag, n_off);
     const uint32_t key = key_of(kind, s);
     if (lane == 0) {
       keys[k] = key;
@@ -145,32 +164,49 @@ __global__ __launch_bounds__(kBlock) void fitness_mfma_kernel(
   }
 }
 
+// The entries of the tiles that are not pairs 1 <= i < j < m: in the
+// diagonal tiles every entry but the pairs (counted in both triangles), in
+// the tiles above them those in row 0 or in a padding column.
+static void mfma_counts(uint32_t m, uint32_t T, uint32_t* n_diag, uint32_t* n_off) {
+  uint32_t nd = 0, no = 0;
+  for (uint32_t i = 0; i < 16 * T; ++i)
+    for (uint32_t j = 0; j < 16 * T; ++j) {
+      const bool pair = i >= 1 && j >= 1 && i < m && j < m && i != j;
+      if (i / 16 == j / 16) nd += pair ? 0u : 1u;
+      else if (i / 16 < j / 16) no += pair ? 0u : 1u;
+    }
+  *n_diag = nd;
+  *n_off = no;
+}
+
 template <int T, int KS>
 static hipError_t launch_mfma_tiles(const ga_config* c, const uint32_t* pop, uint32_t* keys,
                                     uint32_t* comps, RunState* st, uint64_t total, uint32_t grid,
                                     hipStream_t s) {
   const dim3 g(grid), b(kBlock);
+  uint32_t nd, no;
+  mfma_counts(c->m, T, &nd, &no);
   if (comps) {
     hipLaunchKernelGGL((fitness_mfma_kernel<T, KS, kNeedSQ | kNeedABS | kNeedNNZ>), g, b, 0, s,
-                       pop, c->n, c->m, total, c->fitness, keys, comps, st);
+                       pop, c->n, c->m, total, c->fitness, nd, no, keys, comps, st);
     return hipGetLastError();
   }
   switch (needs_of_kind(c->fitness)) {
     case kNeedSQ:
       hipLaunchKernelGGL((fitness_mfma_kernel<T, KS, kNeedSQ>), g, b, 0, s, pop, c->n, c->m,
-                         total, c->fitness, keys, comps, st);
+                         total, c->fitness, nd, no, keys, comps, st);
       break;
     case kNeedABS:
       hipLaunchKernelGGL((fitness_mfma_kernel<T, KS, kNeedABS>), g, b, 0, s, pop, c->n, c->m,
-                         total, c->fitness, keys, comps, st);
+                         total, c->fitness, nd, no, keys, comps, st);
       break;
     case kNeedNNZ:
       hipLaunchKernelGGL((fitness_mfma_kernel<T, KS, kNeedNNZ>), g, b, 0, s, pop, c->n, c->m,
-                         total, c->fitness, keys, comps, st);
+                         total, c->fitness, nd, no, keys, comps, st);
       break;
     default:
       hipLaunchKernelGGL((fitness_mfma_kernel<T, KS, kNeedSQ | kNeedNNZ>), g, b, 0, s, pop,
-                         c->n, c->m, total, c->fitness, keys, comps, st);
+                         c->n, c->m, total, c->fitness, nd, no, keys, comps, st);
   }
   return hipGetLastError();
 }

@@ -31,17 +31,21 @@ def test_fitness_random_all_kinds(m):
     announce("fitness", m, n)
     pop = inputs.random_population(m, n, seed=100 + m)
     dpop = dev_pop_from_int8(pop)
+    # the library's choice of Gram path, and the popcount path forced where
+    # the table picks the matrix cores
+    grams = [0] if m < ga.MFMA_MIN_ORDER else [0, ga.GRAM_PACKED]
     for kind in KINDS:
-        cfg = ga.Config(m=m, n=n, fitness=kind)
-        keys = empty_keys(cfg)
-        comps = torch.zeros((n, 3), dtype=torch.int32, device="cuda")
-        ga.ga_fitness(cfg, dpop, keys, comps)
-        want, want_c = gao.fitness(to_oracle(cfg), pop, with_comps=True)
-        assert np.array_equal(keys_np(keys), want), kind
-        assert np.array_equal(comps.cpu().numpy().view(np.uint32), want_c)
-        keys2 = empty_keys(cfg)
-        ga.ga_fitness(cfg, dpop, keys2)    # without components
-        assert np.array_equal(keys_np(keys2), want)
+        for gram in grams:
+            cfg = ga.Config(m=m, n=n, fitness=kind, flags=gram)
+            keys = empty_keys(cfg)
+            comps = torch.zeros((n, 3), dtype=torch.int32, device="cuda")
+            ga.ga_fitness(cfg, dpop, keys, comps)
+            want, want_c = gao.fitness(to_oracle(cfg), pop, with_comps=True)
+            assert np.array_equal(keys_np(keys), want), (kind, gram)
+            assert np.array_equal(comps.cpu().numpy().view(np.uint32), want_c)
+            keys2 = empty_keys(cfg)
+            ga.ga_fitness(cfg, dpop, keys2)    # without components
+            assert np.array_equal(keys_np(keys2), want)
 
 
 @pytest.mark.parametrize("m", ORDERS)
@@ -53,12 +57,14 @@ def test_fitness_repeat_equals_oracle(m):
     announce("fitness repeat", m, n)
     pop = inputs.random_population(m, n, seed=300 + m)
     dpop = dev_pop_from_int8(pop)
+    grams = [0] if m < ga.MFMA_MIN_ORDER else [0, ga.GRAM_PACKED]
     for i, kind in enumerate(KINDS):
-        cfg = ga.Config(m=m, n=n, fitness=kind)
-        keys = empty_keys(cfg)
-        ga.ga_fitness_repeat(cfg, dpop, keys, reps=1 + 2 * (i % 3))
-        want = gao.fitness(to_oracle(cfg), pop)
-        assert np.array_equal(keys_np(keys), want), kind
+        for gram in grams:
+            cfg = ga.Config(m=m, n=n, fitness=kind, flags=gram)
+            keys = empty_keys(cfg)
+            ga.ga_fitness_repeat(cfg, dpop, keys, reps=1 + 2 * (i % 3))
+            want = gao.fitness(to_oracle(cfg), pop)
+            assert np.array_equal(keys_np(keys), want), (kind, gram)
 
 
 def test_fitness_repeat_full_size_m20_n40000():
