@@ -196,20 +196,24 @@ def time_to_solve(runs=32):
 
 
 def workload_pmc(args):
-    """Short run for hardware-counter passes: the default workload's kernel
-    for one 64-generation chunk, then a plain 256 MiB device copy whose
+    """Short runs for hardware-counter passes: the default workload's kernel
+    for one 64-generation chunk with each lanes-per-child variant (2, 4 and
+    8, the choices a run may keep), then a plain 256 MiB device copy whose
     counter reading calibrates the byte counters."""
     import torch
     import paper_2208_14961_amd as ga
-    cfg = ga.Config(m=20, n=40000, seed=1, fitness=ga.FIT_SQ, max_generations=64, flags=0)
-    bufs = buffers(cfg)
-    r = ga.ga_run(cfg, *bufs)
+    for lanes in (2, 4, 8):
+        cfg = ga.Config(m=20, n=40000, seed=1, fitness=ga.FIT_SQ, max_generations=64,
+                        flags=ga.lanes_flag(lanes))
+        bufs = buffers(cfg)
+        r = ga.ga_run(cfg, *bufs)
     x = torch.ones(64 * 1024 * 1024, dtype=torch.int32, device="cuda")
     y = torch.empty_like(x)
     torch.cuda.synchronize()
     y.copy_(x)
     torch.cuda.synchronize()
-    return {"workload": "counter pass: m=20 n=40000 SQ, 64 generations; 256 MiB copy",
+    return {"workload": "counter pass: m=20 n=40000 SQ, 64 generations with 2, 4 and 8 lanes per "
+                        "child; 256 MiB copy",
             "best_key": r["best_key"], "copy_bytes": 2 * x.numel() * 4}
 
 
@@ -226,19 +230,21 @@ def sources_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per children launch from the committed counter summary, or
-    None when the kernel sources have changed since it was measured."""
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when it holds no record of that kernel or the kernel sources
+    have changed since it was measured."""
     try:
         with open(TRAFFIC_FILE) as f:
             text = f.read()
         block = text.split("```json", 1)[1].split("```", 1)[0]
-        rec = json.loads(block)
+        recs = json.loads(block)
     except (OSError, IndexError, ValueError):
         return None
-    if rec.get("sources_sha256") != sources_digest():
-        return None
-    return rec
+    for rec in recs if isinstance(recs, list) else [recs]:
+        if rec.get("kernel") == kernel and rec.get("sources_sha256") == sources_digest():
+            return rec
+    return None
 
 
 def gram_fitness_metric(reps=1000, repeats=5):
@@ -411,10 +417,8 @@ def bench_default(args):
     ridge = alu_peak * 1e12 / (HBM_PEAK_GBS * 1e9)
     hbm_achieved = n * (rd + wr) / (mean_ms * 1e-3) / 1e9
     kernel = f"children_one_kernel<20, 1u, {ga.ga_tuned_lanes(cfg)}>"
-    tr = measured_traffic()
-    # the counters hold for the variant they were taken on
-    traffic = (tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
-               if tr is not None and tr.get("kernel") == kernel else None)
+    tr = measured_traffic(kernel)  # counters of the variant this run kept
+    traffic = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"] if tr else None
     alu = {"achieved": alu_achieved, "peak": alu_peak, "unit": "TOP/s",
            "frac": alu_achieved / alu_peak, "frac_of_simple_op_peak": alu_achieved / SIMPLE_OP_TOPS,
            "ops_per_eval": ops}
