@@ -245,6 +245,27 @@ ga_status ga_step_static(const ga_config* cfg, const uint32_t* pop_in,
                          uint32_t* keys_out, uint32_t gen_in, void* stream);
 
 /*
+ * The truncation selection of paper mode (Sec. 3.3) as ga_run makes it for
+ * populations up to 65,536: of the n keys of one generation, the n/2
+ * smallest (key, index) pairs, listed in index order.  cfg: a valid
+ * paper-mode config with n <= 65536 (else GA_EINVAL).  Buffers are device
+ * memory owned by the caller:
+ *   keys: n keys, none above the largest key of cfg's fitness kind at its
+ *     order (the search with no threshold known starts there).
+ *   threshold: one word.  In: a key value with at least n/2 keys at or below
+ *     it (in a run, the previous generation's threshold: it never rises), or
+ *     0xFFFFFFFF when none is known; the counts start in a window of 1024
+ *     values below it.  Out: the threshold T, the (n/2)-th smallest key.
+ *   sel: n/2 words: the selected indices in increasing order (every key
+ *     below T and, in index order, the first keys equal to T that make n/2).
+ * ga_run's paper mode writes the same ranks through the generation's parent
+ * permutation instead.  Two launches over tiles of 4096 keys, on the
+ * stream's workspace (calls on one stream are ordered).  Async.
+ */
+ga_status ga_paper_select(const ga_config* cfg, const uint32_t* keys, uint32_t* threshold,
+                          uint32_t* sel, void* stream);
+
+/*
  * A whole run (Sec. 3, the algorithm; Sec. 6 loop): init, fitness, then
  * ga_step until a generation holds a key of 0 (with GA_STOP_ON_FOUND) or
  * max_generations steps were made.  Synchronous: returns when done.

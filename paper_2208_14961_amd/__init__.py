@@ -134,6 +134,7 @@ def lib() -> ctypes.CDLL:
             "ga_tuned_lanes": (u32, [P(_Config)]),
             "ga_step": (i32, [P(_Config), vp, vp, vp, vp, u32, vp]),
             "ga_step_static": (i32, [P(_Config), vp, vp, vp, vp, u32, vp]),
+            "ga_paper_select": (i32, [P(_Config), vp, vp, vp, vp]),
             "ga_run": (i32, [P(_Config), vp, vp, vp, vp, P(_Result), vp]),
             "ga_run_batch": (i32, [P(_Config), u32, P(_Result), vp]),
             "ga_check_invariants": (i32, [P(_Config), vp, P(u32), vp]),
@@ -234,6 +235,15 @@ def ga_step_static(cfg: Config, pop_in, keys_in, pop_out, keys_out, gen_in: int,
     _check(lib().ga_step_static(ctypes.byref(cfg.c()), _dev(pop_in, sh, "pop_in"),
                                 _dev(keys_in, (cfg.n,), "keys_in"), _dev(pop_out, sh, "pop_out"),
                                 _dev(keys_out, (cfg.n,), "keys_out"), gen_in, _stream(stream)))
+
+
+def ga_paper_select(cfg: Config, keys, threshold, sel, stream=None) -> None:
+    """Paper-mode truncation selection of one generation's keys (n <= 65536):
+    sel (int32, n/2) gets the selected indices in increasing order; threshold
+    (int32, 1) holds the previous threshold or -1 and gets this one."""
+    _check(lib().ga_paper_select(ctypes.byref(cfg.c()), _dev(keys, (cfg.n,), "keys"),
+                                 _dev(threshold, (1,), "threshold"),
+                                 _dev(sel, (cfg.n // 2,), "sel"), _stream(stream)))
 
 
 def ga_run(cfg: Config, pop_a, pop_b, keys_a, keys_b, stream=None) -> dict:

@@ -129,6 +129,9 @@ struct Workspace {
   hipEvent_t ev_t[2] = {nullptr, nullptr};  // timing of tuning chunks
   uint32_t* perm = nullptr;        // paper mode: a chunk's slot table
   uint64_t perm_cap = 0;           // its entries
+  PaperWork* pw = nullptr;         // paper mode up to kPaperTileMaxN: the tile selection
+  uint32_t* psel = nullptr;        // and its list of selected indices (psel_cap entries)
+  uint64_t psel_cap = 0;
   // elitism: the next elites' sources, the candidate bitmap and the
   // selection's item list, for populations up to elite_cap
   EliteWork* ew = nullptr;
@@ -278,6 +281,11 @@ static ga_status enqueue_generation(const ga_config* c, const PopDesc& d,
     GA_TRY(launch_elite_select(d, node + 1, w->eitems, s), "elite selection kernel");
     return GA_OK;
   }
+  if (d.psel) {
+    GA_TRY(launch_paper_select(d, node, d.psel, s), "selection kernels");
+    GA_TRY(launch_children_one(d, node, s), "children kernel");
+    return GA_OK;
+  }
   const uint32_t cnt = select_count(c);
   if (cnt > 0)
     GA_TRY(launch_select(d, cnt, w->sel, node, slots, s), "selection kernels");
@@ -415,6 +423,40 @@ ga_status ga_step(const ga_config* cfg, const uint32_t* pop_in,
   return enqueue_generation(cfg, d, w, 0, nullptr, s);
 }
 
+ga_status ga_paper_select(const ga_config* cfg, const uint32_t* keys, uint32_t* threshold,
+                          uint32_t* sel, void* stream) {
+  ga_status st = validate(cfg);
+  if (st != GA_OK) return st;
+  if (cfg->selection != GA_SEL_PAPER || cfg->n > kPaperTileMaxN) {
+    set_error("ga_paper_select: need paper mode and n <= %u", kPaperTileMaxN);
+    return GA_EINVAL;
+  }
+  if (!keys || !threshold || !sel) {
+    set_error("ga_paper_select needs non-NULL buffers");
+    return GA_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  Workspace* w;
+  st = workspace(s, &w);
+  if (st != GA_OK) return st;
+  if (!w->pw) {
+    GA_TRY(hipMalloc(&w->pw, sizeof(PaperWork)), "hipMalloc(selection)");
+    GA_TRY(hipMemset(w->pw, 0, sizeof(PaperWork)), "hipMemset(selection)");
+  }
+  uint32_t* k = const_cast<uint32_t*>(keys);
+  // the selection of generation 1's parents: the keys are generation 0's
+  PopDesc d = make_desc(cfg, nullptr, nullptr, k, k, w->state, 1, 0);
+  d.pw = w->pw;
+  GA_TRY(launch_set_state(w->state, 0, s), "state kernel");
+  // generation 1's selection reads T[0] and writes T[1]
+  GA_TRY(hipMemcpyAsync(&w->pw->T[0], threshold, sizeof(uint32_t), hipMemcpyDeviceToDevice, s),
+         "hipMemcpyAsync(threshold)");
+  GA_TRY(launch_paper_select(d, 0, sel, s), "selection kernels");
+  GA_TRY(hipMemcpyAsync(threshold, &w->pw->T[1], sizeof(uint32_t), hipMemcpyDeviceToDevice, s),
+         "hipMemcpyAsync(threshold)");
+  return GA_OK;
+}
+
 ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
                  uint32_t* keys_a, uint32_t* keys_b, ga_result* out,
                  void* stream) {
@@ -482,6 +524,31 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     d.ew = w->ew;
     d.mark = w->emark;
   }
+  // Paper mode up to kPaperOneBlockMaxN: one block selects (indices and
+  // keys into psel) and the children launch gathers the parents through the
+  // chunk's forward slot table.
+  const bool tiles = table && cfg->n <= kPaperTileMaxN;
+  if (tiles && !w->pw) {
+    GA_TRY(hipMalloc(&w->pw, sizeof(PaperWork)), "hipMalloc(selection)");
+    GA_TRY(hipMemset(w->pw, 0, sizeof(PaperWork)), "hipMemset(selection)");
+  }
+  if (tiles && w->psel_cap < D) {
+    GA_TRY(hipStreamSynchronize(w->capture), "hipStreamSynchronize");
+    if (w->graph) {
+      GA_TRY(hipGraphExecDestroy(w->graph), "hipGraphExecDestroy");
+      w->graph = nullptr;
+    }
+    if (w->psel) GA_TRY(hipFree(w->psel), "hipFree(selected list)");
+    w->psel = nullptr;
+    w->psel_cap = 0;
+    GA_TRY(hipMalloc(&w->psel, (size_t)D * sizeof(uint32_t)), "hipMalloc(selected list)");
+    w->psel_cap = D;
+  }
+  if (tiles) {  // the chunk's table holds pi (forward) for the children launches
+    d.pw = w->pw;
+    d.psel = w->psel;
+    d.pfwd = w->perm;
+  }
   auto capture = [&](const PopDesc& dd) -> ga_status {
     std::vector<char> key(sizeof(PopDesc) + sizeof(ga_config) + sizeof(uint32_t*));
     uint32_t* tab = table ? w->perm : nullptr;
@@ -497,7 +564,9 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     GA_TRY(hipStreamBeginCapture(w->capture, hipStreamCaptureModeThreadLocal),
            "hipStreamBeginCapture");
     ga_status cs = GA_OK;
-    if (tab) cs = hip_status(launch_perm_table(dd, D, chunk, tab, w->capture), "slot table kernel");
+    if (tab)
+      cs = hip_status(launch_perm_table(dd, D, chunk, tab, w->capture, dd.psel != nullptr),
+                      "slot table kernel");
     for (uint32_t i = 0; i < chunk && cs == GA_OK; ++i)
       cs = enqueue_generation(cfg, dd, w, i, tab ? tab + (size_t)i * D : nullptr, w->capture);
     if (cs == GA_OK)
@@ -537,6 +606,11 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
       GA_TRY(launch_select(d, cfg->elite, w->sel, 0, nullptr, w->capture, w->ew->src,
                            &w->ew->kstar),
              "selection kernels");
+    }
+    // no earlier threshold: the first selection searches every key
+    if (tiles) {
+      GA_TRY(hipMemsetAsync(w->pw->T, 0xff, sizeof(w->pw->T), w->capture),
+             "hipMemsetAsync(selection)");
     }
   }
   if (explore) {

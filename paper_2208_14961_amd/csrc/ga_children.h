@@ -363,8 +363,8 @@ __device__ __forceinline__ uint32_t lanes_fitness(const uint32_t* me, uint32_t l
 // children (M*W words each).  Lanes of pairs past the last compute a copy of
 // the last pair and store nothing.  NT: nontemporal stores of the child.
 template <int M, uint32_t NEED, int L_, bool NT>
-__device__ __forceinline__ unsigned long long child(const PopDesc& d,
-                                                   uint32_t G, uint32_t* lds) {
+__device__ __forceinline__ unsigned long long child(const PopDesc& d, uint32_t G,
+                                                   uint32_t node, uint32_t* lds) {
   using Q = Lanes<M, L_>;
   constexpr int L = Q::L, NP = Q::NP;
   constexpr uint32_t MW = M * Q::W;
@@ -392,9 +392,18 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d,
   // this child's first parent (its columns before the cut) and slot
   const uint32_t* first;
   uint32_t dst;
+  uint32_t pslot = ~0u, pkey = 0;  // with d.psel: the parent slot this lane group fills
   if (d.paper) {
     const uint32_t N = d.n / 4;
-    first = pout + (size_t)(c ? p + N : p) * MW;
+    const uint32_t ps = c ? p + N : p;
+    if (d.psel) {  // parent slot ps receives sel[pi(ps)] of generation G - 1
+      const uint32_t src = d.psel[d.pfwd[(size_t)node * (2 * N) + ps]];
+      first = pin + (size_t)src * MW;
+      pkey = kin[src];
+      pslot = ps;
+    } else {
+      first = pout + (size_t)ps * MW;
+    }
     dst = (c ? 3u * N : 2u * N) + p;
   } else {
     first = pin + (size_t)tournament(d, G, p, c, sel, kin) * MW;
@@ -410,6 +419,14 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d,
     f[4 * s + 1] = v.y;
     f[4 * s + 2] = v.z;
     f[4 * s + 3] = v.w;
+  }
+  if (pslot != ~0u && valid) {  // the parent itself, into its slot of generation G
+    uint4* p4 = reinterpret_cast<uint4*>(pout + (size_t)pslot * MW);
+#pragma unroll
+    for (int s = 0; s < NP; ++s)
+      if (Q::has(s, l))
+        store_row<NT>(p4 + l + L * s, make_uint4(f[4 * s], f[4 * s + 1], f[4 * s + 2], f[4 * s + 3]));
+    if (l == 0) store_key<NT>(kout + pslot, pkey);
   }
   // column-exchange crossover (Sec. 3.4): columns >= cut from the sibling's
   // first parent
@@ -538,7 +555,7 @@ __global__ __launch_bounds__(kChildBlock) void children_one_kernel(PopDesc d,
   children_block(d, node, [&](uint32_t G) __attribute__((always_inline)) {
     EliteRow er{make_uint4(0, 0, 0, 0), 0u};
     if (d.ew) er = load_first_elite<M>(d, G);
-    const unsigned long long b = child<M, NEED, L, true>(d, G, lds);
+    const unsigned long long b = child<M, NEED, L, true>(d, G, node, lds);
     if (d.ew) copy_elites<M, true>(d, G, er);
     return b;
   });
@@ -558,7 +575,7 @@ __global__ __launch_bounds__(kChildBlock) void children_multi_kernel(
   __shared__ __align__(16) uint32_t lds[Q::CPB * M * Q::W];
   const PopDesc d = descs[block_pop[blockIdx.x]];
   children_block(d, node, [&](uint32_t G) __attribute__((always_inline)) {
-    return child<M, 0, L, false>(d, G, lds);
+    return child<M, 0, L, false>(d, G, node, lds);
   });
 }
 

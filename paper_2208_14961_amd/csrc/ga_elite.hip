@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "ga_common.h"
+#include "ga_scan.h"
 
 namespace ga {
 
@@ -31,59 +32,6 @@ struct EliteArgs {
   uint32_t* item_slot;     // slots of list entries past the LDS
   uint32_t n, e, node, max_gen, stop_on_found, one_level;
 };
-
-constexpr int kEliteWaves = kEliteBlock / 64;
-
-// Inclusive prefix sum over the 64 lanes of a wave: shifts by 1, 2, 4 and 8
-// within each row of 16 lanes (DPP, lanes shifted in from outside the row
-// read 0), then the totals of the rows before (read from lanes 15, 31, 47).
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_shr(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
-}
-__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
-  v += dpp_shr<0x111>(v);  // row_shr:1
-  v += dpp_shr<0x112>(v);  // row_shr:2
-  v += dpp_shr<0x114>(v);  // row_shr:4
-  v += dpp_shr<0x118>(v);  // row_shr:8
-  const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
-  const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
-  const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
-  const uint32_t row = (threadIdx.x & 63u) >> 4;
-  return v + (row > 0 ? r0 : 0u) + (row > 1 ? r1 : 0u) + (row > 2 ? r2 : 0u);
-}
-
-// Exclusive prefix sums of two values over the block, and their totals.
-// Each call site passes its own ID, so the wave totals of one call are never
-// overwritten by a later one: one barrier per call.
-template <int ID>
-__device__ __forceinline__ uint2 block_scan2(uint32_t a, uint32_t b, uint2* total) {
-  __shared__ uint2 s_wave[kEliteWaves];
-  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  const uint32_t ia = wave_inclusive_scan(a), ib = wave_inclusive_scan(b);
-  if (lane == 63) s_wave[wave] = make_uint2(ia, ib);
-  __syncthreads();
-  uint2 base = make_uint2(0, 0), tot = make_uint2(0, 0);
-#pragma unroll
-  for (uint32_t w = 0; w < kEliteWaves; ++w) {
-    const uint2 x = s_wave[w];
-    if (w < wave) {
-      base.x += x.x;
-      base.y += x.y;
-    }
-    tot.x += x.x;
-    tot.y += x.y;
-  }
-  *total = tot;
-  return make_uint2(base.x + ia - a, base.y + ib - b);
-}
-template <int ID>
-__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* total) {
-  uint2 t;
-  const uint2 r = block_scan2<ID>(v, 0u, &t);
-  *total = t.x;
-  return r.x;
-}
 
 // Adds the lanes' bins (those with `valid`) into an LDS histogram: one LDS
 // atomic per wave, which serializes lanes on the same bin in the LDS itself.
@@ -122,7 +70,7 @@ __device__ __forceinline__ void find_bin(const uint32_t* hist, uint32_t target,
     sum += v[i];
   }
   uint32_t total;
-  uint32_t run = block_scan<ID>(sum, &total);
+  uint32_t run = block_scan<kEliteBlock, ID>(sum, &total);
 #pragma unroll
   for (int i = 0; i < per; ++i) {
     if (run < target && target <= run + v[i]) {
@@ -181,7 +129,7 @@ __device__ __forceinline__ void select_items(const EliteArgs& a, uint32_t nitems
     eq += k == T;
   }
   uint2 tot;
-  const uint2 off = block_scan2<3>(less, eq, &tot);
+  const uint2 off = block_scan2<kEliteBlock, 3>(less, eq, &tot);
   uint32_t lb = off.x, eb = off.y;
   for (uint32_t i = i0; i < i1; ++i) {
     const uint32_t k = key_at(i);
@@ -245,7 +193,7 @@ __global__ __launch_bounds__(kEliteBlock) void elite_select_kernel(EliteArgs a) 
   for (uint32_t u = 0; u < kWordsHeld; ++u) cnt += __popc(held[u]);
   for (uint32_t w = w0 + kWordsHeld; w < w1; ++w) cnt += __popc(a.mark[w]);
   uint32_t total;
-  uint32_t at = e + block_scan<0>(cnt, &total);
+  uint32_t at = e + block_scan<kEliteBlock, 0>(cnt, &total);
   auto list = [&](uint32_t w, uint32_t bits) {
     while (bits) {
       const uint32_t slot = w * 32u + (uint32_t)(__ffs(bits) - 1);

@@ -81,6 +81,23 @@ struct EliteWork {
                              // the one before (increasing)
 };
 
+// Paper mode in ga_run up to kPaperTileMaxN individuals (ga_paper.hip): a
+// launch over tiles of kPaperTile keys counts each tile's keys in a window of
+// kPaperBins values below the previous threshold; a second launch over the
+// tiles finds the threshold in every tile and lists the selected indices in
+// index order.
+constexpr uint32_t kPaperTile = 4096;
+constexpr uint32_t kPaperBins = 1024;
+constexpr uint32_t kPaperTileMaxN = 65536;
+constexpr uint32_t kPaperMaxTiles = kPaperTileMaxN / kPaperTile;
+struct PaperWork {
+  uint32_t T[2];    // threshold of the selection of generation g's parents in
+                    // T[g & 1]; ~0 before the first
+  uint32_t pad[62];
+  uint32_t hist[kPaperMaxTiles][kPaperBins + 1];  // per tile: keys at top - d, then
+                                                  // keys below the window
+};
+
 struct PopDesc {
   uint32_t* pop_a;
   uint32_t* pop_b;
@@ -109,6 +126,12 @@ struct PopDesc {
   EliteWork* ew;         // ga_run with elitism: the children launch copies the elites
                          // and marks candidates (null: elites copied by the selection)
   uint32_t* mark;        // with ew: bitmap over slots, a child below ew->kstar
+  PaperWork* pw;          // ga_run paper mode up to kPaperTileMaxN: the tile
+                         // selection's work area
+  uint32_t* psel;        // with pw: the selected indices of generation G - 1 in
+                         // index order (2N); parent slot s of G receives
+                         // psel[pfwd[s]]
+  const uint32_t* pfwd;  // with pw: the chunk's forward slot table, rows of 2N
 };
 
 // Workspace of the selection pipeline of one population.
@@ -155,15 +178,19 @@ hipError_t launch_select(const PopDesc& d, uint32_t count, SelWork* ws,
                          uint32_t node, const uint32_t* slots, hipStream_t s,
                          uint32_t* src_out = nullptr, uint32_t* kstar_out = nullptr);
 // paper mode: pi^-1 over [0, count) for the generations of launches
-// 0 .. nodes-1 of a chunk, row by row into out[nodes][count]
+// 0 .. nodes-1 of a chunk, row by row into out[nodes][count]; forward: pi
 hipError_t launch_perm_table(const PopDesc& d, uint32_t count, uint32_t nodes,
-                             uint32_t* out, hipStream_t s);
+                             uint32_t* out, hipStream_t s, bool forward = false);
 // ga_run with elitism: the elites of generation gen_base + node + 1 of d
 // chosen from generation gen_base + node (see EliteWork), from its elites
 // and its marked children.  item_slot: n entries of scratch.  (The first
 // generation's come from launch_select with src_out.)
 hipError_t launch_elite_select(const PopDesc& d, uint32_t node, uint32_t* item_slot,
                                hipStream_t s);
+// Paper mode up to kPaperTileMaxN, parents of generation gen_base + node + 1
+// (d.pw holds the previous threshold, or ~0): the threshold and the tile
+// offsets, then sel[rho] = the rho-th selected index in index order.
+hipError_t launch_paper_select(const PopDesc& d, uint32_t node, uint32_t* sel, hipStream_t s);
 // children of every population in descs (device array), all of order m
 hipError_t launch_children(const PopDesc* descs_dev, const uint32_t* block_pop,
                            uint32_t total_blocks, uint32_t m, uint32_t lanes,

@@ -226,6 +226,21 @@ __device__ __forceinline__ uint32_t feistel_inverse(uint64_t seed, uint32_t G,
   return (L << h) | R;
 }
 
+// One forward evaluation: round r maps (L, R) to (R, L xor f_r(R)).
+__device__ __forceinline__ uint32_t feistel_forward(uint64_t seed, uint32_t G,
+                                                    uint32_t h, uint32_t x) {
+  const uint32_t mask = (1u << h) - 1u;
+  uint32_t L = x >> h, R = x & mask;
+  for (int r = 0; r < 8; ++r) {
+    const U4 u = draw_block(seed, kStreamPerm, G, R, (uint32_t)r >> 2);
+    const uint32_t f = u[(uint32_t)r & 3u] & mask;
+    const uint32_t nr = L ^ f;
+    L = R;
+    R = nr;
+  }
+  return (L << h) | R;
+}
+
 __device__ uint32_t perm_inverse(uint64_t seed, uint32_t G, uint32_t D,
                                  uint32_t y) {
   const uint32_t h = feistel_half_bits(D);
@@ -248,9 +263,12 @@ __device__ uint32_t perm_inverse(uint64_t seed, uint32_t G, uint32_t D,
 // a pool of kPermPerWave elements and a lane that ends a walk takes the
 // next element of the pool: the wave runs for about the pool's total walk
 // length over 64 plus one walk, not 64 times its longest walk.  Element t
-// (row t / D, rank t % D) gets exactly perm_inverse's value.
+// (row t / D, rank t % D) gets exactly perm_inverse's value; with FWD, row
+// t / D holds instead pi(s) of every parent slot s = t % D (the forward
+// network, walked the same way).
 constexpr uint32_t kPermPerWave = 512;
 
+template <bool FWD>
 __global__ __launch_bounds__(kBlock) void perm_table_kernel(const RunState* st,
                                                             uint64_t seed, uint32_t D,
                                                             uint32_t nodes,
@@ -271,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void perm_table_kernel(const RunState* st,
   uint64_t it = 0;
   while (__ballot(busy) != 0ull || next < end) {
     if (busy) {
-      x = feistel_inverse(seed, G, h, x);
+      x = FWD ? feistel_forward(seed, G, h, x) : feistel_inverse(seed, G, h, x);
       if (x < D || ++it == limit) {
         out[e] = x;
         busy = false;
@@ -293,11 +311,16 @@ __global__ __launch_bounds__(kBlock) void perm_table_kernel(const RunState* st,
 }
 
 hipError_t launch_perm_table(const PopDesc& d, uint32_t count, uint32_t nodes,
-                             uint32_t* out, hipStream_t s) {
+                             uint32_t* out, hipStream_t s, bool forward) {
   const uint64_t total = (uint64_t)count * nodes;
   const uint64_t waves = (total + kPermPerWave - 1) / kPermPerWave;
-  hipLaunchKernelGGL(perm_table_kernel, dim3(cdiv(waves * 64, kBlock)), dim3(kBlock), 0, s,
-                     d.state, d.seed, count, nodes, out);
+  const dim3 grid(cdiv(waves * 64, kBlock)), block(kBlock);
+  if (forward)
+    hipLaunchKernelGGL(perm_table_kernel<true>, grid, block, 0, s, d.state, d.seed, count,
+                       nodes, out);
+  else
+    hipLaunchKernelGGL(perm_table_kernel<false>, grid, block, 0, s, d.state, d.seed, count,
+                       nodes, out);
   return hipGetLastError();
 }
 

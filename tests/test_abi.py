@@ -175,3 +175,19 @@ def test_run_rejects_unbounded_budget_before_device_work():
     assert L.ga_run(ctypes.byref(cfg), fake, ctypes.c_void_p(512), fake,
                     ctypes.c_void_p(512), ctypes.byref(out), None) == ga.GA_EINVAL
     assert "max_generations" in L.ga_last_error().decode()
+
+
+def test_paper_select_rejects_bad_arguments_before_device_work():
+    """ga_paper_select takes paper-mode configs up to 65,536 individuals and
+    non-NULL buffers; it checks before any device work."""
+    L = ga.lib()
+    fake = ctypes.c_void_p(256)  # never dereferenced
+    paper = ga.Config(m=20, n=40000, selection=ga.SEL_PAPER, fitness=ga.FIT_F2).c()
+    tour = ga.Config(m=20, n=40000).c()
+    big = ga.Config(m=20, n=65540, selection=ga.SEL_PAPER, fitness=ga.FIT_F2).c()
+    assert L.ga_paper_select(ctypes.byref(tour), fake, fake, fake, None) == ga.GA_EINVAL
+    assert L.ga_paper_select(ctypes.byref(big), fake, fake, fake, None) == ga.GA_EINVAL
+    assert "65536" in L.ga_last_error().decode()
+    assert L.ga_paper_select(ctypes.byref(paper), None, fake, fake, None) == ga.GA_EINVAL
+    assert L.ga_paper_select(ctypes.byref(paper), fake, None, fake, None) == ga.GA_EINVAL
+    assert L.ga_paper_select(ctypes.byref(paper), fake, fake, None, None) == ga.GA_EINVAL

@@ -1,5 +1,7 @@
 """GPU-vs-oracle parity of every entry point of libga.  All results are
 integers and must match bit for bit."""
+import zlib
+
 import numpy as np
 import pytest
 
@@ -334,6 +336,58 @@ def test_step_elite_with_ties():
     _step_chain(cfg, 3, start=pop)
 
 
+def _paper_select_case(name, n):
+    """Keys of one generation and a starting threshold (None: none known)."""
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    D = n // 2
+    if name == "oracle_gen0":  # the initial keys of the m = 20 Table 2 run
+        cfg = gao.Config(m=20, n=n, seed=9020, selection=gao.SEL_PAPER, fitness=gao.FIT_F2)
+        return gao.fitness(cfg, gao.init_population(cfg)), None
+    if name.startswith("spread"):
+        keys = rng.integers(100_000, 300_000, n).astype(np.uint32)
+    elif name == "ties":
+        keys = rng.integers(0, 50, n).astype(np.uint32)
+    elif name == "all_equal":
+        keys = np.full(n, 77, dtype=np.uint32)
+    else:
+        keys = rng.integers(0, 5000, n).astype(np.uint32)
+    T = int(np.sort(keys)[D - 1])
+    prev = {"spread_below_window": T + 1000,     # keys below the 16-bit window
+            "spread_window_missed": T + 100_000,  # T below the window: the slow path
+            "spread_unaligned": T + 300,
+            "ties": 60, "all_equal": 77, "prev_is_T": T, "prev_above": T + 37,
+            "cold": None}[name]
+    return keys, prev
+
+
+@pytest.mark.parametrize("name,n", [
+    ("oracle_gen0", 40000), ("cold", 4), ("cold", 400), ("prev_is_T", 1028),
+    ("prev_above", 40000), ("spread_below_window", 4096), ("spread_below_window", 65536),
+    ("spread_window_missed", 40000), ("spread_unaligned", 40000), ("ties", 40000),
+    ("ties", 65536), ("all_equal", 2052), ("cold", 65536),
+])
+def test_paper_select(name, n):
+    """The tile truncation selection (Sec. 3.3) of ga_run's paper mode on its
+    own: threshold and selected set against the oracle's selection of the n/2
+    smallest (key, index), from a cold start, from thresholds at or above the
+    answer, with keys below the 1024-value window it counts in, with the
+    answer below that window, and with long runs of equal keys."""
+    torch = torch_cuda()
+    announce("paper select", name, n)
+    keys, prev = _paper_select_case(name, n)
+    D = n // 2
+    # order 64, SQ: keys up to 8,000,256, above every key drawn here
+    cfg = ga.Config(m=64, n=n, seed=1, selection=ga.SEL_PAPER, fitness=ga.FIT_SQ)
+    kd = torch.from_numpy(keys.view(np.int32).copy()).cuda()
+    if name == "spread_unaligned":  # keys at a 4-byte offset: the scalar tile loads
+        kd = torch.cat([torch.zeros(1, dtype=torch.int32, device="cuda"), kd])[1:]
+    sel = torch.full((D,), -7, dtype=torch.int32, device="cuda")
+    thr = torch.tensor([-1 if prev is None else prev], dtype=torch.int32, device="cuda")
+    ga.ga_paper_select(cfg, kd, thr, sel)
+    assert int(keys_np(thr)[0]) == int(np.sort(keys)[D - 1])
+    assert np.array_equal(keys_np(sel), np.sort(gao.select_set(keys, D)))
+
+
 @pytest.mark.parametrize("m,N,nc,nr,kind", [
     (12, 250, 1, 2, ga.FIT_F2), (20, 100, 4, 2, ga.FIT_F1), (16, 1, 2, 2, ga.FIT_F2),
     (40, 64, 2, 8, ga.FIT_F2), (8, 4096, 3, 2, ga.FIT_F2),
@@ -415,6 +469,19 @@ def test_run_plain_m8_config():
               flags=ga.STOP_ON_FOUND | ga.MUT_SHARED),
     ga.Config(m=52, n=2000, seed=18, selection=ga.SEL_PAPER, fitness=ga.FIT_F1,
               xo_threshold=1 << 32, mut_threshold=1 << 32, nc=2, nr=3, max_generations=70,
+              flags=0),
+    # the one-block paper selection at its largest population (64 keys per
+    # thread), and just past it (the multi-launch selection with a slot table)
+    ga.Config(m=16, n=65536, seed=19, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
+              xo_threshold=1 << 32, mut_threshold=1 << 32, nc=1, nr=2, max_generations=40,
+              flags=0),
+    ga.Config(m=8, n=65540, seed=20, selection=ga.SEL_PAPER, fitness=ga.FIT_F1,
+              xo_threshold=1 << 32, mut_threshold=1 << 32, nc=1, nr=2, max_generations=10,
+              flags=0),
+    # the Table 2 configuration at m = 20 (40,000 matrices, F2, NC = 4, NR = 2),
+    # shortened to 300 generations
+    ga.Config(m=20, n=40000, seed=9020, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
+              xo_threshold=1 << 32, mut_threshold=1 << 32, nc=4, nr=2, max_generations=300,
               flags=0),
     # 64 x 2N > 2^24: no chunk slot table, the scatter walks the permutation
     ga.Config(m=4, n=600000, seed=17, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
