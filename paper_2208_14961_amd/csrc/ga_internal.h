@@ -253,6 +253,8 @@ struct RunBuffers {
   uint32_t* keys_b = nullptr;
   SelWork* sel = nullptr;  // runs with elitism or paper mode
   uint32_t* slots = nullptr;  // paper-mode runs: a chunk's slot table
+  PaperWork* pw = nullptr;    // paper-mode runs up to kPaperTileMaxN with a table:
+  uint32_t* psel = nullptr;   // the tile selection and its list (then slots holds pi)
   void* base = nullptr;   // single allocation holding all of them
 };
 size_t run_bytes(const ga_config* c);
@@ -275,7 +277,6 @@ class MultiLaunch {
   // descs: one per run (state pointers set); rebuilds and uploads the tables
   ga_status set(const PopDesc* descs, uint32_t count, hipStream_t s);
   // launch `node` of a chunk: one generation of every run still going
-  ga_status enqueue_generation(uint32_t node, hipStream_t s);
   // a chunk of `gens` launches and the gen_base advance, as one graph
   // launch on s (captured on first use after set(); s must not be the null
   // stream)

@@ -33,11 +33,18 @@ static size_t table_bytes(const ga_config* c) {
   return entries <= kMaxPermTable ? align256(entries * sizeof(uint32_t)) : 0;
 }
 
+// Paper-mode runs with a table and at most kPaperTileMaxN individuals select
+// as ga_run does (ga_paper.hip); their table then holds pi, not pi^-1.
+static size_t tile_bytes(const ga_config* c) {
+  if (!table_bytes(c) || c->n > kPaperTileMaxN) return 0;
+  return align256(sizeof(PaperWork)) + align256((size_t)(c->n / 2) * sizeof(uint32_t));
+}
+
 size_t run_bytes(const ga_config* c) {
   const size_t pop = (size_t)c->n * c->m * words_per_col(c->m) * 4;
   const size_t keys = (size_t)c->n * 4;
   return 2 * align256(pop) + 2 * align256(keys) + (selects(c) ? align256(sizeof(SelWork)) : 0) +
-         table_bytes(c);
+         table_bytes(c) + tile_bytes(c);
 }
 
 ga_status alloc_run(const ga_config* c, RunBuffers* b) {
@@ -54,6 +61,11 @@ ga_status alloc_run(const ga_config* c, RunBuffers* b) {
   b->sel = sel ? reinterpret_cast<SelWork*>(base + 2 * pop + 2 * keys) : nullptr;
   b->slots = table_bytes(c) ? reinterpret_cast<uint32_t*>(base + 2 * pop + 2 * keys + sel)
                             : nullptr;
+  if (tile_bytes(c)) {
+    char* t = base + 2 * pop + 2 * keys + sel + table_bytes(c);
+    b->pw = reinterpret_cast<PaperWork*>(t);
+    b->psel = reinterpret_cast<uint32_t*>(t + align256(sizeof(PaperWork)));
+  }
   return GA_OK;
 }
 
@@ -62,6 +74,11 @@ PopDesc run_desc(const ga_config* c, const RunBuffers& b, RunState* st) {
                         (c->flags & GA_STOP_ON_FOUND) ? 1u : 0u);
   d.sel = b.sel;
   d.slots = b.slots;
+  if (b.pw) {
+    d.pw = b.pw;
+    d.psel = b.psel;
+    d.pfwd = b.slots;
+  }
   return d;
 }
 
@@ -168,6 +185,14 @@ ga_status MultiLaunch::enqueue_group(const Group& g, uint32_t node, bool tables,
                                      hipStream_t s) {
   for (uint32_t i = 0; i < g.ndesc; ++i) {
     const PopDesc& d = g.hdesc[i];
+    if (d.pw) {  // its children launch reads the chunk's table of pi
+      if (!tables) {
+        set_error("internal: a tile-selecting run without its chunk table");
+        return GA_EINVAL;
+      }
+      GA_TRY(launch_paper_select(d, node, d.psel, s), "selection kernels");
+      continue;
+    }
     if (!d.sel) continue;
     const uint32_t* row =
         (tables && d.paper && d.slots) ? d.slots + (size_t)node * (d.n / 2) : nullptr;
@@ -176,15 +201,6 @@ ga_status MultiLaunch::enqueue_group(const Group& g, uint32_t node, bool tables,
   }
   GA_TRY(launch_children(g.desc, g.map, g.nblocks, g.m, g.lanes, node, s),
          "children kernel");
-  return GA_OK;
-}
-
-ga_status MultiLaunch::enqueue_generation(uint32_t node, hipStream_t s) {
-  for (Group& g : groups_) {
-    if (!g.nblocks) continue;
-    const ga_status st = enqueue_group(g, node, false, s);
-    if (st != GA_OK) return st;
-  }
   return GA_OK;
 }
 
@@ -230,7 +246,8 @@ ga_status MultiLaunch::launch_chunk(uint32_t gens, hipStream_t s) {
       for (uint32_t j = 0; j < gr.ndesc && st == GA_OK && tables; ++j) {
         const PopDesc& d = gr.hdesc[j];
         if (d.paper && d.slots)
-          st = hip_status(launch_perm_table(d, d.n / 2, gens, d.slots, b), "slot table kernel");
+          st = hip_status(launch_perm_table(d, d.n / 2, gens, d.slots, b, d.pw != nullptr),
+                          "slot table kernel");
       }
       for (uint32_t i = 0; i < gens && st == GA_OK; ++i) st = enqueue_group(gr, i, tables, b);
       if (st == GA_OK)
@@ -259,6 +276,8 @@ static ga_status start_run(const ga_config* c, const RunBuffers& b,
                            RunState* st, hipStream_t s) {
   // the selection passes expect zero histograms on entry (and leave them so)
   if (b.sel) GA_TRY(hipMemsetAsync(b.sel, 0, sizeof(SelWork), s), "hipMemsetAsync(selection)");
+  // the tile selection: no threshold yet
+  if (b.pw) GA_TRY(hipMemsetAsync(b.pw->T, 0xff, sizeof(b.pw->T), s), "hipMemsetAsync(selection)");
   GA_TRY(launch_reset_state(st, s), "state kernel");
   GA_TRY(launch_init(c, b.pop_a, s), "init kernel");
   GA_TRY(launch_fitness(c, b.pop_a, b.keys_a, nullptr, st, s), "fitness kernel");
