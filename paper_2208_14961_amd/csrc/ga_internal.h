@@ -94,8 +94,9 @@ struct PaperWork {
   uint32_t T[2];    // threshold of the selection of generation g's parents in
                     // T[g & 1]; ~0 before the first
   uint32_t pad[62];
-  uint32_t hist[kPaperMaxTiles][kPaperBins + 1];  // per tile: keys at top - d, then
-                                                  // keys below the window
+  uint32_t hist[kPaperMaxTiles][kPaperBins + 1];  // per tile, entry d: its keys with
+                                                  // d <= top - key < kPaperBins;
+                                                  // last: its keys below that window
 };
 
 struct PopDesc {

@@ -10,13 +10,16 @@
 // Two launches over tiles of kPaperTile keys (one block of 1024 threads, four
 // keys a thread):
 //  * count: each tile counts its keys at top - d for d < kPaperBins (LDS
-//    bins) and below that window; top is the previous selection's T.  T never
+//    bins) and below that window, and writes for each d its keys at distance
+//    d or more (a suffix sum) and its keys below; top is the previous
+//    selection's T.  T never
 //    increases from one generation to the next (the 2N parents of a
 //    generation carry keys <= the T that selected them), so T lies in
 //    [0, top], and in practice within the window.
-//  * list: every tile sums the tiles' bins (a few KB, cached), finds T and r
-//    and the counts of selected keys below T and equal to T in the tiles
-//    before it, ranks its own selected keys with a block scan, and writes
+//  * list: every tile adds the tiles' suffix sums (thread t takes d = t: the
+//    count of keys <= top - d without a scan), finds T and r and the counts of
+//    selected keys below T and equal to T in the tiles before it (two words
+//    of each), ranks its own selected keys with a block scan, and writes
 //    sel[rho] = index for rank rho.  Without a previous T, top is the
 //    largest key of the fitness kind; if T lies below the window, each tile
 //    finds it by counting all keys (the slow path).
@@ -110,7 +113,12 @@ __global__ __launch_bounds__(kPaperBlock) void paper_count_kernel(PaperArgs a) {
   add(k4.w);
   uint32_t which = 0;
   const uint32_t tile_below = paper_block_sum(below, red, which);  // its barrier ends the adds
-  pw->hist[b][tid] = h[tid];
+  // thread t: d = kPaperBins - 1 - t, so the inclusive prefix over threads is
+  // the tile's keys at distance d or more
+  const uint32_t d = kPaperBins - 1 - tid, hd = h[d];
+  uint32_t total;
+  const uint32_t cum = block_scan<kPaperBlock, 3>(hd, &total) + hd;
+  pw->hist[b][d] = cum;
   if (tid == 0) pw->hist[b][kPaperBins] = tile_below;
 }
 
@@ -123,56 +131,52 @@ __global__ __launch_bounds__(kPaperBlock) void paper_list_kernel(PaperArgs a) {
   const uint32_t i0 = b * kPaperTile + 4 * tid;
   const uint32_t prev = pw->T[(G - 1) & 1u];
   const uint32_t top = prev == ~0u ? a.key_bound : prev;
-  // every load at once: this tile's keys, bin d = kPaperBins - 1 - t of every
-  // tile (a prefix over threads is then a sum over the smaller keys), and
-  // tile t's count below the window
+  // every load at once: this tile's keys, every tile's suffix sum at d = t,
+  // and every tile's count below the window (the same words in every thread)
   const uint4 k4 = tile_keys(keys, a.n, i0);
-  const uint32_t d = kPaperBins - 1 - tid;
-  uint32_t hv[kPaperMaxTiles];
+  const uint32_t d = tid;
+  uint32_t S = 0, below = 0;
 #pragma unroll
-  for (uint32_t t = 0; t < kPaperMaxTiles; ++t) hv[t] = t < a.ntiles ? pw->hist[t][d] : 0u;
-  const uint32_t tb = tid < a.ntiles ? pw->hist[tid][kPaperBins] : 0u;
+  for (uint32_t t = 0; t < kPaperMaxTiles; ++t) {
+    if (t < a.ntiles) {
+      S += pw->hist[t][d];
+      below += pw->hist[t][kPaperBins];
+    }
+  }
   __shared__ uint32_t red[2][kPaperBlock / 64];
-  __shared__ uint32_t s_below[kPaperMaxTiles], s_eq[kPaperMaxTiles];
-  __shared__ uint32_t s_part[kPaperBlock / 64][kPaperMaxTiles];
+  __shared__ uint32_t s_le[kPaperBins];
   __shared__ uint32_t s_T, s_r, s_ds, s_found, s_less0, s_eq0;
   uint32_t which = 0;
-  if (tid < kPaperMaxTiles) s_below[tid] = tb;
+  const uint32_t le = below + S;  // keys <= top - d
+  s_le[d] = le;
   if (tid == 0) s_found = 0;
-  const uint32_t below = paper_block_sum(tb, red, which);
-  uint32_t Hd = 0;
-#pragma unroll
-  for (uint32_t t = 0; t < kPaperMaxTiles; ++t) Hd += hv[t];
-  uint32_t total;
-  const uint32_t above_d = block_scan<kPaperBlock, 0>(Hd, &total);  // keys at top - d', d' > d
-  const uint32_t lt = below + above_d, le = lt + Hd;  // keys < top - d, keys <= top - d
+  __syncthreads();
+  const uint32_t lt = d + 1 < kPaperBins ? s_le[d + 1] : below;  // keys < top - d
   if (below < D && le >= D && lt < D) {  // at most one thread: T = top - d
     s_T = top - d;
     s_r = D - lt;
     s_ds = d;
     s_found = 1;
-#pragma unroll
-    for (uint32_t t = 0; t < kPaperMaxTiles; ++t) s_eq[t] = hv[t];
   }
   __syncthreads();
   if (s_found) {
-    // tiles before this one: keys below the window or at d > d*, keys at d*
-    const uint32_t ds = s_ds;
-#pragma unroll
-    for (uint32_t t = 0; t < kPaperMaxTiles; ++t) {
-      const uint32_t c = wave_total(t < b && d > ds ? hv[t] : 0u);
-      if (lane == 0) s_part[wave][t] = c;
-    }
-    __syncthreads();
-    if (tid == 0) {
+    // the tiles before this one: keys below the window or at distance > d*,
+    // and keys at d* (two suffix sums of each, cached)
+    if (wave == 0) {
+      const uint32_t ds = s_ds;
       uint32_t l = 0, e = 0;
-      for (uint32_t t = 0; t < b; ++t) {
-        l += s_below[t];
-        e += s_eq[t];
-        for (uint32_t w = 0; w < kPaperBlock / 64; ++w) l += s_part[w][t];
+      if (lane < b) {
+        const uint32_t* hx = pw->hist[lane];
+        const uint32_t c0 = hx[ds], c1 = ds + 1 < kPaperBins ? hx[ds + 1] : 0u;
+        l = hx[kPaperBins] + c1;
+        e = c0 - c1;
       }
-      s_less0 = l;
-      s_eq0 = e;
+      l = wave_total(l);
+      e = wave_total(e);
+      if (lane == 0) {
+        s_less0 = l;
+        s_eq0 = e;
+      }
     }
   } else {
     // slow path: T below the window (or fewer than 2N keys at or below top):
