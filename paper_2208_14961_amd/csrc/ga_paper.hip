@@ -135,16 +135,20 @@ __global__ __launch_bounds__(kPaperBlock) void paper_list_kernel(PaperArgs a) {
   // and every tile's count below the window (the same words in every thread)
   const uint4 k4 = tile_keys(keys, a.n, i0);
   const uint32_t d = tid;
-  uint32_t S = 0, below = 0;
+  uint32_t hv[kPaperMaxTiles], S = 0, below = 0;
 #pragma unroll
   for (uint32_t t = 0; t < kPaperMaxTiles; ++t) {
-    if (t < a.ntiles) {
-      S += pw->hist[t][d];
-      below += pw->hist[t][kPaperBins];
-    }
+    hv[t] = t < a.ntiles ? pw->hist[t][d] : 0u;
+    below += t < a.ntiles ? pw->hist[t][kPaperBins] : 0u;
   }
+  const uint32_t own_below = tid < a.ntiles ? pw->hist[tid][kPaperBins] : 0u;
+#pragma unroll
+  for (uint32_t t = 0; t < kPaperMaxTiles; ++t) S += hv[t];
   __shared__ uint32_t red[2][kPaperBlock / 64];
   __shared__ uint32_t s_le[kPaperBins];
+  __shared__ uint32_t s_c[2][kPaperMaxTiles];  // each tile's suffix sums at d* and d* + 1
+  __shared__ uint32_t s_below[kPaperMaxTiles];
+  if (tid < kPaperMaxTiles) s_below[tid] = own_below;
   __shared__ uint32_t s_T, s_r, s_ds, s_found, s_less0, s_eq0;
   uint32_t which = 0;
   const uint32_t le = below + S;  // keys <= top - d
@@ -152,24 +156,29 @@ __global__ __launch_bounds__(kPaperBlock) void paper_list_kernel(PaperArgs a) {
   if (tid == 0) s_found = 0;
   __syncthreads();
   const uint32_t lt = d + 1 < kPaperBins ? s_le[d + 1] : below;  // keys < top - d
+  if (tid < kPaperMaxTiles) s_c[1][tid] = 0;  // d* + 1 past the window
   if (below < D && le >= D && lt < D) {  // at most one thread: T = top - d
     s_T = top - d;
     s_r = D - lt;
     s_ds = d;
     s_found = 1;
+#pragma unroll
+    for (uint32_t t = 0; t < kPaperMaxTiles; ++t) s_c[0][t] = hv[t];
   }
   __syncthreads();
   if (s_found) {
     // the tiles before this one: keys below the window or at distance > d*,
-    // and keys at d* (two suffix sums of each, cached)
+    // and keys at d*, from the suffix sums the threads of d* and d* + 1 hold
+    if (d == s_ds + 1) {
+#pragma unroll
+      for (uint32_t t = 0; t < kPaperMaxTiles; ++t) s_c[1][t] = hv[t];
+    }
+    __syncthreads();
     if (wave == 0) {
-      const uint32_t ds = s_ds;
       uint32_t l = 0, e = 0;
       if (lane < b) {
-        const uint32_t* hx = pw->hist[lane];
-        const uint32_t c0 = hx[ds], c1 = ds + 1 < kPaperBins ? hx[ds + 1] : 0u;
-        l = hx[kPaperBins] + c1;
-        e = c0 - c1;
+        l = s_below[lane] + s_c[1][lane];
+        e = s_c[0][lane] - s_c[1][lane];
       }
       l = wave_total(l);
       e = wave_total(e);
