@@ -16,7 +16,7 @@ __host__ __device__ constexpr uint32_t col_words(uint32_t m) {
 
 // The largest key of a fitness kind at order m (all columns equal: every
 // pair has |c_i . c_j| = m).
-inline uint64_t max_key(uint32_t m, uint32_t kind) {
+__host__ __device__ inline uint64_t max_key(uint32_t m, uint32_t kind) {
   const uint64_t P = (uint64_t)(m - 1) * (m - 2) / 2, mm = m;
   switch (kind) {
     case GA_FIT_SQ: return P * mm * mm;
@@ -192,6 +192,10 @@ hipError_t launch_elite_select(const PopDesc& d, uint32_t node, uint32_t* item_s
 // (d.pw holds the previous threshold, or ~0): the threshold and the tile
 // offsets, then sel[rho] = the rho-th selected index in index order.
 hipError_t launch_paper_select(const PopDesc& d, uint32_t node, uint32_t* sel, hipStream_t s);
+// The same for several runs in two launches: block b takes tile (e & 15) of
+// run descs[e >> 4], e = tiles[b], into that run's d.psel.
+hipError_t launch_paper_select_multi(const PopDesc* descs_dev, const uint32_t* tiles,
+                                     uint32_t nblocks, uint32_t node, hipStream_t s);
 // children of every population in descs (device array), all of order m
 hipError_t launch_children(const PopDesc* descs_dev, const uint32_t* block_pop,
                            uint32_t total_blocks, uint32_t m, uint32_t lanes,
@@ -295,6 +299,8 @@ class MultiLaunch {
     uint32_t* hmap = nullptr;
     size_t cap_desc = 0, cap_map = 0;
     uint32_t ndesc = 0, nblocks = 0;
+    uint32_t npaper = 0;             // tile-selection blocks: map[nblocks ..], each
+                                     // (run << 4 | tile)
   };
   // launch `node` for one group: its runs' selections (paper mode reading
   // row `node` of the slot tables when `tables`), then its children

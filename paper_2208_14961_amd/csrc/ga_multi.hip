@@ -142,6 +142,12 @@ ga_status MultiLaunch::set(const PopDesc* descs, uint32_t count,
     }
     g.nblocks = (uint32_t)map.size();
     g.ndesc = (uint32_t)ds.size();
+    // the tile selection's blocks of the group's paper-mode runs follow
+    for (uint32_t j = 0; j < ds.size(); ++j)
+      if (ds[j].pw)
+        for (uint32_t t = 0; t < (ds[j].n + kPaperTile - 1) / kPaperTile; ++t)
+          map.push_back(j << 4 | t);
+    g.npaper = (uint32_t)map.size() - g.nblocks;
     if (ds.empty()) continue;
     // The launches on s read these tables, so they are uploaded on s itself
     // (stream order puts the copy before the launches) from pinned staging
@@ -183,17 +189,17 @@ ga_status MultiLaunch::set(const PopDesc* descs, uint32_t count,
 // group's children launch.
 ga_status MultiLaunch::enqueue_group(const Group& g, uint32_t node, bool tables,
                                      hipStream_t s) {
+  if (g.npaper) {  // every tile-selecting run of the group in two launches
+    if (!tables) {  // their children launch reads the chunk's table of pi
+      set_error("internal: a tile-selecting run without its chunk table");
+      return GA_EINVAL;
+    }
+    GA_TRY(launch_paper_select_multi(g.desc, g.map + g.nblocks, g.npaper, node, s),
+           "selection kernels");
+  }
   for (uint32_t i = 0; i < g.ndesc; ++i) {
     const PopDesc& d = g.hdesc[i];
-    if (d.pw) {  // its children launch reads the chunk's table of pi
-      if (!tables) {
-        set_error("internal: a tile-selecting run without its chunk table");
-        return GA_EINVAL;
-      }
-      GA_TRY(launch_paper_select(d, node, d.psel, s), "selection kernels");
-      continue;
-    }
-    if (!d.sel) continue;
+    if (d.pw || !d.sel) continue;
     const uint32_t* row =
         (tables && d.paper && d.slots) ? d.slots + (size_t)node * (d.n / 2) : nullptr;
     GA_TRY(launch_select(d, d.paper ? d.n / 2 : d.elite, d.sel, node, row, s),

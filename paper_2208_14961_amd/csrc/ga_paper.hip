@@ -86,14 +86,34 @@ __device__ __forceinline__ uint32_t paper_block_sum(uint32_t v, uint32_t (*buf)[
   return s;
 }
 
-__global__ __launch_bounds__(kPaperBlock) void paper_count_kernel(PaperArgs a) {
+// The arguments of a run's selection from its descriptor.
+__device__ __host__ __forceinline__ PaperArgs paper_args(const PopDesc& d, uint32_t node,
+                                                         uint32_t* sel) {
+  PaperArgs a;
+  a.keys_a = d.keys_a;
+  a.keys_b = d.keys_b;
+  a.st = d.state;
+  a.pw = d.pw;
+  a.sel = sel;
+  a.n = d.n;
+  a.D = d.n / 2;
+  a.node = node;
+  a.max_gen = d.max_gen;
+  a.stop_on_found = d.stop_on_found;
+  a.key_bound = (uint32_t)max_key(d.m, d.kind);
+  a.ntiles = (d.n + kPaperTile - 1) / kPaperTile;
+  return a;
+}
+
+// Tile b of the count launch.
+__device__ __forceinline__ void paper_count_tile(const PaperArgs& a, uint32_t b) {
   uint32_t G;
-  if (!paper_generation(a, &G)) return;  // uniform over the launch
+  if (!paper_generation(a, &G)) return;  // uniform over the block
   const uint32_t* keys = ((G - 1) & 1u) ? a.keys_b : a.keys_a;
   PaperWork* pw = a.pw;
   const uint32_t prev = pw->T[(G - 1) & 1u];
   const uint32_t top = prev == ~0u ? a.key_bound : prev;
-  const uint32_t tid = threadIdx.x, b = blockIdx.x;
+  const uint32_t tid = threadIdx.x;
   __shared__ uint32_t h[kPaperBins];
   __shared__ uint32_t red[2][kPaperBlock / 64];
   h[tid] = 0;
@@ -122,12 +142,13 @@ __global__ __launch_bounds__(kPaperBlock) void paper_count_kernel(PaperArgs a) {
   if (tid == 0) pw->hist[b][kPaperBins] = tile_below;
 }
 
-__global__ __launch_bounds__(kPaperBlock) void paper_list_kernel(PaperArgs a) {
+// Tile b of the list launch.
+__device__ __forceinline__ void paper_list_tile(const PaperArgs& a, uint32_t b) {
   uint32_t G;
   if (!paper_generation(a, &G)) return;
   const uint32_t* keys = ((G - 1) & 1u) ? a.keys_b : a.keys_a;
   PaperWork* pw = a.pw;
-  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, D = a.D, b = blockIdx.x;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, D = a.D;
   const uint32_t i0 = b * kPaperTile + 4 * tid;
   const uint32_t prev = pw->T[(G - 1) & 1u];
   const uint32_t top = prev == ~0u ? a.key_bound : prev;
@@ -239,23 +260,41 @@ __global__ __launch_bounds__(kPaperBlock) void paper_list_kernel(PaperArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kPaperBlock) void paper_count_kernel(PaperArgs a) {
+  paper_count_tile(a, blockIdx.x);
+}
+__global__ __launch_bounds__(kPaperBlock) void paper_list_kernel(PaperArgs a) {
+  paper_list_tile(a, blockIdx.x);
+}
+
+// Several runs: block b takes tile (e & 15) of run descs[e >> 4], e = tiles[b].
+__global__ __launch_bounds__(kPaperBlock) void paper_count_multi_kernel(
+    const PopDesc* __restrict__ descs, const uint32_t* __restrict__ tiles, uint32_t node) {
+  const uint32_t e = tiles[blockIdx.x];
+  const PopDesc& d = descs[e >> 4];
+  paper_count_tile(paper_args(d, node, d.psel), e & 15u);
+}
+__global__ __launch_bounds__(kPaperBlock) void paper_list_multi_kernel(
+    const PopDesc* __restrict__ descs, const uint32_t* __restrict__ tiles, uint32_t node) {
+  const uint32_t e = tiles[blockIdx.x];
+  const PopDesc& d = descs[e >> 4];
+  paper_list_tile(paper_args(d, node, d.psel), e & 15u);
+}
+
 hipError_t launch_paper_select(const PopDesc& d, uint32_t node, uint32_t* sel, hipStream_t s) {
   if (d.n > kPaperTileMaxN) return hipErrorInvalidValue;
-  PaperArgs a;
-  a.keys_a = d.keys_a;
-  a.keys_b = d.keys_b;
-  a.st = d.state;
-  a.pw = d.pw;
-  a.sel = sel;
-  a.n = d.n;
-  a.D = d.n / 2;
-  a.node = node;
-  a.max_gen = d.max_gen;
-  a.stop_on_found = d.stop_on_found;
-  a.key_bound = (uint32_t)max_key(d.m, d.kind);
-  a.ntiles = (d.n + kPaperTile - 1) / kPaperTile;
+  const PaperArgs a = paper_args(d, node, sel);
   hipLaunchKernelGGL(paper_count_kernel, dim3(a.ntiles), dim3(kPaperBlock), 0, s, a);
   hipLaunchKernelGGL(paper_list_kernel, dim3(a.ntiles), dim3(kPaperBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_paper_select_multi(const PopDesc* descs_dev, const uint32_t* tiles,
+                                     uint32_t nblocks, uint32_t node, hipStream_t s) {
+  hipLaunchKernelGGL(paper_count_multi_kernel, dim3(nblocks), dim3(kPaperBlock), 0, s, descs_dev,
+                     tiles, node);
+  hipLaunchKernelGGL(paper_list_multi_kernel, dim3(nblocks), dim3(kPaperBlock), 0, s, descs_dev,
+                     tiles, node);
   return hipGetLastError();
 }
 

@@ -611,6 +611,28 @@ def test_run_batch_with_selection():
         _equals_oracle_run(cfg, got)
 
 
+def test_run_batch_paper_runs_share_selection_launches():
+    """Several paper-mode runs of one order, of one to three selection tiles
+    (4,096 keys each) and different kinds and flags, select in the same two
+    launches per generation: each equals its run in the oracle."""
+    torch_cuda()
+    paper = dict(selection=ga.SEL_PAPER, xo_threshold=1 << 32, mut_threshold=1 << 32)
+    cfgs = [
+        ga.Config(m=12, n=8200, seed=71, fitness=ga.FIT_F2, nc=1, nr=2, max_generations=60,
+                  flags=0, **paper),
+        ga.Config(m=12, n=4096, seed=72, fitness=ga.FIT_F1, nc=2, nr=1, max_generations=45,
+                  flags=0, **paper),
+        ga.Config(m=12, n=400, seed=73, fitness=ga.FIT_F2, nc=1, nr=1, max_generations=200,
+                  flags=ga.STOP_ON_FOUND, **paper),
+        ga.Config(m=12, n=12000, seed=74, fitness=ga.FIT_SQ, nc=3, nr=2, max_generations=33,
+                  flags=ga.MUT_SHARED, **paper),
+        ga.Config(m=12, n=900, seed=75, max_generations=30),
+    ]
+    announce("batch paper runs sharing launches", len(cfgs))
+    for cfg, got in zip(cfgs, ga.ga_run_batch(cfgs)):
+        _equals_oracle_run(cfg, got)
+
+
 def test_server_with_selection():
     torch_cuda()
     cfgs = _selecting_configs()
