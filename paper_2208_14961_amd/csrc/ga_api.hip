@@ -523,6 +523,7 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
   if (elites) {
     d.ew = w->ew;
     d.mark = w->emark;
+    d.eitems = w->eitems;
   }
   // Paper mode up to kPaperOneBlockMaxN: one block selects (indices and
   // keys into psel) and the children launch gathers the parents through the

@@ -147,7 +147,7 @@ __device__ __forceinline__ void select_items(const EliteArgs& a, uint32_t nitems
 constexpr uint32_t kWordsHeld = 8;
 constexpr uint32_t kKeysHeld = 2;
 
-__global__ __launch_bounds__(kEliteBlock) void elite_select_kernel(EliteArgs a) {
+__device__ __forceinline__ void elite_select_block(const EliteArgs& a) {
   const uint32_t tid = threadIdx.x, e = a.e;
   const uint32_t nw = (a.n + 31u) / 32u;
   const uint32_t per = (nw + kEliteBlock - 1) / kEliteBlock;
@@ -262,8 +262,9 @@ __global__ __launch_bounds__(kEliteBlock) void elite_select_kernel(EliteArgs a) 
   }
 }
 
-hipError_t launch_elite_select(const PopDesc& d, uint32_t node, uint32_t* item_slot,
-                               hipStream_t s) {
+// The arguments of a run's elite selection from its descriptor.
+__device__ __host__ __forceinline__ EliteArgs elite_args(const PopDesc& d, uint32_t node,
+                                                         uint32_t* item_slot) {
   EliteArgs a;
   a.keys_a = d.keys_a;
   a.keys_b = d.keys_b;
@@ -277,7 +278,30 @@ hipError_t launch_elite_select(const PopDesc& d, uint32_t node, uint32_t* item_s
   a.max_gen = d.max_gen;
   a.stop_on_found = d.stop_on_found;
   a.one_level = max_key(d.m, d.kind) < 4096 ? 1u : 0u;
-  hipLaunchKernelGGL(elite_select_kernel, dim3(1), dim3(kEliteBlock), 0, s, a);
+  return a;
+}
+
+__global__ __launch_bounds__(kEliteBlock) void elite_select_kernel(EliteArgs a) {
+  elite_select_block(a);
+}
+
+__global__ __launch_bounds__(kEliteBlock) void elite_select_multi_kernel(
+    const PopDesc* __restrict__ descs, const uint32_t* __restrict__ runs, uint32_t node) {
+  const PopDesc& d = descs[runs[blockIdx.x]];
+  elite_select_block(elite_args(d, node, d.eitems));
+}
+
+hipError_t launch_elite_select(const PopDesc& d, uint32_t node, uint32_t* item_slot,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(elite_select_kernel, dim3(1), dim3(kEliteBlock), 0, s,
+                     elite_args(d, node, item_slot));
+  return hipGetLastError();
+}
+
+hipError_t launch_elite_select_multi(const PopDesc* descs_dev, const uint32_t* runs,
+                                     uint32_t count, uint32_t node, hipStream_t s) {
+  hipLaunchKernelGGL(elite_select_multi_kernel, dim3(count), dim3(kEliteBlock), 0, s, descs_dev,
+                     runs, node);
   return hipGetLastError();
 }
 

@@ -127,6 +127,7 @@ struct PopDesc {
   EliteWork* ew;         // ga_run with elitism: the children launch copies the elites
                          // and marks candidates (null: elites copied by the selection)
   uint32_t* mark;        // with ew: bitmap over slots, a child below ew->kstar
+  uint32_t* eitems;      // with ew: n words, slots of candidate lists past the LDS
   PaperWork* pw;          // ga_run paper mode up to kPaperTileMaxN: the tile
                          // selection's work area
   uint32_t* psel;        // with pw: the selected indices of generation G - 1 in
@@ -188,6 +189,10 @@ hipError_t launch_perm_table(const PopDesc& d, uint32_t count, uint32_t nodes,
 // generation's come from launch_select with src_out.)
 hipError_t launch_elite_select(const PopDesc& d, uint32_t node, uint32_t* item_slot,
                                hipStream_t s);
+// The same for several runs in one launch (block b: run descs[runs[b]], its
+// d.eitems as the scratch).
+hipError_t launch_elite_select_multi(const PopDesc* descs_dev, const uint32_t* runs,
+                                     uint32_t count, uint32_t node, hipStream_t s);
 // Paper mode up to kPaperTileMaxN, parents of generation gen_base + node + 1
 // (d.pw holds the previous threshold, or ~0): the threshold and the tile
 // offsets, then sel[rho] = the rho-th selected index in index order.
@@ -260,6 +265,9 @@ struct RunBuffers {
   uint32_t* slots = nullptr;  // paper-mode runs: a chunk's slot table
   PaperWork* pw = nullptr;    // paper-mode runs up to kPaperTileMaxN with a table:
   uint32_t* psel = nullptr;   // the tile selection and its list (then slots holds pi)
+  EliteWork* ew = nullptr;    // elitist runs: elites from a candidate list, as in
+  uint32_t* emark = nullptr;  // ga_run (the candidate bitmap and the long-list
+  uint32_t* eitems = nullptr; // slots)
   void* base = nullptr;   // single allocation holding all of them
 };
 size_t run_bytes(const ga_config* c);
@@ -301,6 +309,8 @@ class MultiLaunch {
     uint32_t ndesc = 0, nblocks = 0;
     uint32_t npaper = 0;             // tile-selection blocks: map[nblocks ..], each
                                      // (run << 4 | tile)
+    uint32_t nelite = 0;             // candidate-list elitist runs: map[nblocks +
+                                     // npaper ..], each a run
   };
   // launch `node` for one group: its runs' selections (paper mode reading
   // row `node` of the slot tables when `tables`), then its children

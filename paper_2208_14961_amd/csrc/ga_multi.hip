@@ -40,11 +40,19 @@ static size_t tile_bytes(const ga_config* c) {
   return align256(sizeof(PaperWork)) + align256((size_t)(c->n / 2) * sizeof(uint32_t));
 }
 
+// Elitist runs choose their elites as ga_run does: from the previous elites
+// and the children marked below the largest elite key (ga_elite.hip).
+static size_t elite_bytes(const ga_config* c) {
+  if (c->selection != GA_SEL_TOURNAMENT || c->elite == 0) return 0;
+  return align256(sizeof(EliteWork)) + align256(((size_t)c->n + 31) / 32 * 4) +
+         align256((size_t)c->n * 4);
+}
+
 size_t run_bytes(const ga_config* c) {
   const size_t pop = (size_t)c->n * c->m * words_per_col(c->m) * 4;
   const size_t keys = (size_t)c->n * 4;
   return 2 * align256(pop) + 2 * align256(keys) + (selects(c) ? align256(sizeof(SelWork)) : 0) +
-         table_bytes(c) + tile_bytes(c);
+         table_bytes(c) + tile_bytes(c) + elite_bytes(c);
 }
 
 ga_status alloc_run(const ga_config* c, RunBuffers* b) {
@@ -66,6 +74,13 @@ ga_status alloc_run(const ga_config* c, RunBuffers* b) {
     b->pw = reinterpret_cast<PaperWork*>(t);
     b->psel = reinterpret_cast<uint32_t*>(t + align256(sizeof(PaperWork)));
   }
+  if (elite_bytes(c)) {
+    char* t = base + 2 * pop + 2 * keys + sel + table_bytes(c) + tile_bytes(c);
+    b->ew = reinterpret_cast<EliteWork*>(t);
+    t += align256(sizeof(EliteWork));
+    b->emark = reinterpret_cast<uint32_t*>(t);
+    b->eitems = reinterpret_cast<uint32_t*>(t + align256(((size_t)c->n + 31) / 32 * 4));
+  }
   return GA_OK;
 }
 
@@ -78,6 +93,11 @@ PopDesc run_desc(const ga_config* c, const RunBuffers& b, RunState* st) {
     d.pw = b.pw;
     d.psel = b.psel;
     d.pfwd = b.slots;
+  }
+  if (b.ew) {
+    d.ew = b.ew;
+    d.mark = b.emark;
+    d.eitems = b.eitems;
   }
   return d;
 }
@@ -148,6 +168,10 @@ ga_status MultiLaunch::set(const PopDesc* descs, uint32_t count,
         for (uint32_t t = 0; t < (ds[j].n + kPaperTile - 1) / kPaperTile; ++t)
           map.push_back(j << 4 | t);
     g.npaper = (uint32_t)map.size() - g.nblocks;
+    // then the group's candidate-list elitist runs
+    for (uint32_t j = 0; j < ds.size(); ++j)
+      if (ds[j].ew) map.push_back(j);
+    g.nelite = (uint32_t)map.size() - g.nblocks - g.npaper;
     if (ds.empty()) continue;
     // The launches on s read these tables, so they are uploaded on s itself
     // (stream order puts the copy before the launches) from pinned staging
@@ -199,7 +223,7 @@ ga_status MultiLaunch::enqueue_group(const Group& g, uint32_t node, bool tables,
   }
   for (uint32_t i = 0; i < g.ndesc; ++i) {
     const PopDesc& d = g.hdesc[i];
-    if (d.pw || !d.sel) continue;
+    if (d.pw || d.ew || !d.sel) continue;
     const uint32_t* row =
         (tables && d.paper && d.slots) ? d.slots + (size_t)node * (d.n / 2) : nullptr;
     GA_TRY(launch_select(d, d.paper ? d.n / 2 : d.elite, d.sel, node, row, s),
@@ -207,6 +231,10 @@ ga_status MultiLaunch::enqueue_group(const Group& g, uint32_t node, bool tables,
   }
   GA_TRY(launch_children(g.desc, g.map, g.nblocks, g.m, g.lanes, node, s),
          "children kernel");
+  // the elites of the next generation, from the elites and the marked children
+  if (g.nelite)
+    GA_TRY(launch_elite_select_multi(g.desc, g.map + g.nblocks + g.npaper, g.nelite, node + 1, s),
+           "elite selection kernel");
   return GA_OK;
 }
 
@@ -284,9 +312,19 @@ static ga_status start_run(const ga_config* c, const RunBuffers& b,
   if (b.sel) GA_TRY(hipMemsetAsync(b.sel, 0, sizeof(SelWork), s), "hipMemsetAsync(selection)");
   // the tile selection: no threshold yet
   if (b.pw) GA_TRY(hipMemsetAsync(b.pw->T, 0xff, sizeof(b.pw->T), s), "hipMemsetAsync(selection)");
+  // candidate-list elitism: a clear bitmap (the elites of generation 1 are
+  // chosen below, once the initial keys exist)
+  if (b.ew)
+    GA_TRY(hipMemsetAsync(b.emark, 0, ((size_t)c->n + 31) / 32 * sizeof(uint32_t), s),
+           "hipMemsetAsync(candidate bitmap)");
   GA_TRY(launch_reset_state(st, s), "state kernel");
   GA_TRY(launch_init(c, b.pop_a, s), "init kernel");
   GA_TRY(launch_fitness(c, b.pop_a, b.keys_a, nullptr, st, s), "fitness kernel");
+  if (b.ew) {  // the first generation's elites, from the whole initial population
+    const PopDesc d = run_desc(c, b, st);
+    GA_TRY(launch_select(d, c->elite, b.sel, 0, nullptr, s, b.ew->src, &b.ew->kstar),
+           "selection kernels");
+  }
   return GA_OK;
 }
 
