@@ -279,9 +279,11 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
 
 /*
  * Several independent runs advanced together: one children launch per order
- * and generation covers every active run of that order; runs with elitism
- * or paper mode add their own selection launches, on a workspace of their
- * own.  Synchronous.  cfgs, outs: host arrays of count entries.  The library
+ * and generation covers every active run of that order.  Selection is shared
+ * the same way: the order's elitist runs choose their elites in one launch,
+ * its paper-mode runs (up to 65,536 individuals) select in one pair of
+ * launches; larger paper-mode runs add launches of their own.  Each run's
+ * selection works in its own allocation.  Synchronous.  cfgs, outs: host arrays of count entries.  The library
  * allocates the populations.  Every run's result equals what ga_run gives
  * for it alone.
  */
