@@ -138,10 +138,31 @@ struct Workspace {
   uint32_t* emark = nullptr;
   uint32_t* eitems = nullptr;      // slots of long candidate lists: elite_cap words
   uint64_t elite_cap = 0;
-  // cached graph of one chunk of generations, valid for `graph_key`
+  // graphs of one chunk of generations, each valid for its key (the launch
+  // descriptor, config and table); the last used last.  `graph` is the one
+  // the last capture() chose.
+  struct CachedGraph {
+    std::vector<char> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<CachedGraph> graphs;
   hipGraphExec_t graph = nullptr;
-  std::vector<char> graph_key;
 };
+
+// Graphs kept per workspace: the lanes-per-child candidates of one run shape.
+constexpr size_t kGraphCache = 4;
+
+static hipError_t drop_graphs(Workspace* w) {
+  hipError_t e = hipSuccess;
+  for (auto& c : w->graphs)
+    if (c.exec) {
+      const hipError_t x = hipGraphExecDestroy(c.exec);
+      if (e == hipSuccess) e = x;
+    }
+  w->graphs.clear();
+  w->graph = nullptr;
+  return e;
+}
 
 static std::mutex g_ws_mu;
 static std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
@@ -490,10 +511,7 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
   if (table && w->perm_cap < (uint64_t)D * chunk) {
     // a cached graph may still run with the old table
     GA_TRY(hipStreamSynchronize(w->capture), "hipStreamSynchronize");
-    if (w->graph) {
-      GA_TRY(hipGraphExecDestroy(w->graph), "hipGraphExecDestroy");
-      w->graph = nullptr;
-    }
+    GA_TRY(drop_graphs(w), "hipGraphExecDestroy");
     if (w->perm) GA_TRY(hipFree(w->perm), "hipFree(slot table)");
     w->perm = nullptr;
     w->perm_cap = 0;
@@ -505,10 +523,7 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
   const bool elites = cfg->selection == GA_SEL_TOURNAMENT && cfg->elite > 0 && nchunks > 0;
   if (elites && w->elite_cap < cfg->n) {
     GA_TRY(hipStreamSynchronize(w->capture), "hipStreamSynchronize");
-    if (w->graph) {
-      GA_TRY(hipGraphExecDestroy(w->graph), "hipGraphExecDestroy");
-      w->graph = nullptr;
-    }
+    GA_TRY(drop_graphs(w), "hipGraphExecDestroy");
     if (w->emark) GA_TRY(hipFree(w->emark), "hipFree(candidate bitmap)");
     if (w->eitems) GA_TRY(hipFree(w->eitems), "hipFree(candidate list)");
     w->emark = nullptr;
@@ -535,10 +550,7 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
   }
   if (tiles && w->psel_cap < D) {
     GA_TRY(hipStreamSynchronize(w->capture), "hipStreamSynchronize");
-    if (w->graph) {
-      GA_TRY(hipGraphExecDestroy(w->graph), "hipGraphExecDestroy");
-      w->graph = nullptr;
-    }
+    GA_TRY(drop_graphs(w), "hipGraphExecDestroy");
     if (w->psel) GA_TRY(hipFree(w->psel), "hipFree(selected list)");
     w->psel = nullptr;
     w->psel_cap = 0;
@@ -556,11 +568,19 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     memcpy(key.data(), &dd, sizeof(PopDesc));
     memcpy(key.data() + sizeof(PopDesc), cfg, sizeof(ga_config));
     memcpy(key.data() + sizeof(PopDesc) + sizeof(ga_config), &tab, sizeof tab);
-    if (w->graph && w->graph_key == key) return GA_OK;
-    if (w->graph) {
-      GA_TRY(hipGraphExecDestroy(w->graph), "hipGraphExecDestroy");
-      w->graph = nullptr;
+    for (size_t i = 0; i < w->graphs.size(); ++i)
+      if (w->graphs[i].key == key) {  // most recently used last
+        Workspace::CachedGraph c = std::move(w->graphs[i]);
+        w->graphs.erase(w->graphs.begin() + i);
+        w->graphs.push_back(std::move(c));
+        w->graph = w->graphs.back().exec;
+        return GA_OK;
+      }
+    if (w->graphs.size() >= kGraphCache) {
+      GA_TRY(hipGraphExecDestroy(w->graphs.front().exec), "hipGraphExecDestroy");
+      w->graphs.erase(w->graphs.begin());
     }
+    w->graph = nullptr;
     hipGraph_t g;
     GA_TRY(hipStreamBeginCapture(w->capture, hipStreamCaptureModeThreadLocal),
            "hipStreamBeginCapture");
@@ -575,9 +595,11 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     hipError_t ce = hipStreamEndCapture(w->capture, &g);
     if (cs != GA_OK) return cs;
     GA_TRY(ce, "hipStreamEndCapture");
-    GA_TRY(hipGraphInstantiate(&w->graph, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    hipGraphExec_t exec = nullptr;
+    GA_TRY(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
     GA_TRY(hipGraphDestroy(g), "hipGraphDestroy");
-    w->graph_key = key;
+    w->graphs.push_back(Workspace::CachedGraph{key, exec});
+    w->graph = exec;
     return GA_OK;
   };
   // Lanes per child: forced by the config, or measured on this run's own
@@ -615,14 +637,22 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     }
   }
   if (explore) {
-    float best_ms = 0;
-    uint32_t best = d.lanes;
-    for (uint32_t ci = 0; ci < cands.size() && !finished; ++ci) {
+    // Each candidate: one chunk to settle (a new graph's first launch,
+    // caches), then timed chunks.  With enough chunks the candidates are
+    // timed twice, in the order c1 .. ck ck .. c1, so that a drift of the
+    // generation time over the run (selection work changes as the
+    // population converges) weighs on every candidate alike.
+    const uint32_t nc = (uint32_t)cands.size();
+    const bool twice = nchunks >= 3 * (uint64_t)nc + 1;
+    std::vector<float> total(nc, 0.f);
+    std::vector<uint32_t> timed(nc, 0);
+    const uint32_t visits = twice ? 2 * nc : nc;
+    for (uint32_t k = 0; k < visits && !finished; ++k) {
+      const uint32_t ci = k < nc ? k : 2 * nc - 1 - k;
       set_lanes(&d, cands[ci]);
       st = capture(d);
       if (st != GA_OK) return st;
-      // one chunk to settle (a new graph's first launch, caches), one timed
-      for (int rep = 0; rep < 2 && !finished; ++rep) {
+      for (int rep = k < nc ? 0 : 1; rep < 2 && !finished; ++rep) {
         GA_TRY(hipEventRecord(w->ev_t[0], w->capture), "hipEventRecord");
         GA_TRY(hipGraphLaunch(w->graph, w->capture), "hipGraphLaunch");
         GA_TRY(hipEventRecord(w->ev_t[1], w->capture), "hipEventRecord");
@@ -635,11 +665,23 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
         if (rep == 1) {
           float ms = 0;
           GA_TRY(hipEventElapsedTime(&ms, w->ev_t[0], w->ev_t[1]), "hipEventElapsedTime");
-          if (ci == 0 || ms < best_ms) {
-            best_ms = ms;
-            best = cands[ci];
-          }
+          total[ci] += ms;
+          ++timed[ci];
         }
+      }
+    }
+    // the least mean time among the candidates timed (all of them, equally
+    // often, unless the run ended during the measurement)
+    uint32_t best = d.lanes;
+    float best_ms = 0.f;
+    bool any = false;
+    for (uint32_t ci = 0; ci < nc; ++ci) {
+      if (!timed[ci]) continue;
+      const float mean = total[ci] / (float)timed[ci];
+      if (!any || mean < best_ms) {
+        best_ms = mean;
+        best = cands[ci];
+        any = true;
       }
     }
     if (!finished) tuned_store(tkey, best);  // a measurement cut short is not kept

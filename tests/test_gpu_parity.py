@@ -532,8 +532,17 @@ def test_run_paper_study_cells(m, nc, nr, kind, gens):
 
 
 @pytest.mark.parametrize("cfg", [
+    # each candidate timed once (fewer than 3 chunks per candidate + 1)
     ga.Config(m=20, n=1500, seed=31, max_generations=400, flags=0),
     ga.Config(m=40, n=400, seed=32, elite=5, fitness=ga.FIT_ABS, max_generations=300, flags=0),
+    # each timed twice, in the order c1 .. ck ck .. c1
+    ga.Config(m=20, n=1500, seed=33, max_generations=700, flags=0),
+    ga.Config(m=40, n=400, seed=34, elite=5, fitness=ga.FIT_ABS, max_generations=450, flags=0),
+    ga.Config(m=16, n=2000, seed=35, selection=ga.SEL_PAPER, fitness=ga.FIT_F1,
+              xo_threshold=1 << 32, mut_threshold=1 << 32, nc=2, nr=2, max_generations=650,
+              flags=0),
+    # a solution found while the candidates are still being timed
+    ga.Config(m=8, n=1024, seed=36, max_generations=700),
 ])
 def test_run_tunes_lanes_inside_the_run(cfg):
     """A run long enough to measure every lanes-per-child variant on its own
