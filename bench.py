@@ -301,6 +301,30 @@ def elite_run_metric():
             "best_key": r["best_key"]}
 
 
+def paper_mode_metric(steps=2):
+    """The paper's truncation-selection GA in the Table 2 configuration at
+    m=20 (Sec. 4.2: 40,000 matrices, crossover and mutation on every
+    offspring, NC=4, NR=2, 10^4 generations, no stop), keys F1 and F2: whole
+    runs, median of `steps` after a warm one, beside the paper's seconds."""
+    import statistics
+    import paper_2208_14961_amd as ga
+    m, N, G = 20, 10_000, 10_000
+    bufs = buffers(ga.Config(m=m, n=4 * N, selection=ga.SEL_PAPER))
+    out = {"workload": "paper mode, m=20, 40,000 matrices, NC=4, NR=2, 10^4 generations, "
+                       "seed 9020, no stop on found"}
+    for name, kind in (("F1", ga.FIT_F1), ("F2", ga.FIT_F2)):
+        cfg = ga.Config(m=m, n=4 * N, seed=9_000 + m, selection=ga.SEL_PAPER, fitness=kind,
+                        xo_threshold=1 << 32, mut_threshold=1 << 32, nc=4, nr=2,
+                        max_generations=G, flags=0)
+        ga.ga_run(cfg, *bufs)  # warm: the run's lanes-per-child measurement
+        times = [timed_runs(cfg, bufs, 1) for _ in range(max(1, steps))]
+        sec = statistics.median(times)
+        paper_s = PAPER_TABLE2[m][0 if name == "F1" else 1]
+        out[name] = {"seconds": sec, "generations_per_s": G / sec, "us_per_generation": 1e6 * sec / G,
+                     "paper_seconds": paper_s, "speedup_vs_paper": paper_s / sec}
+    return out
+
+
 def bench_elite(args):
     """The elitist run alone, `--steps` timed runs after a warm one."""
     import torch
@@ -459,6 +483,7 @@ def bench_default(args):
     out["time_to_solve"] = time_to_solve()
     out["gram_fitness_kernel"] = gram_fitness_metric()
     out["elite_run"] = elite_run_metric()
+    out["paper_mode"] = paper_mode_metric()
     if not args.no_multi:
         out["batched"] = batched_leg(steps=2)
         print("default: batched leg done", file=sys.stderr, flush=True)
