@@ -575,10 +575,10 @@ __global__ __launch_bounds__(kChildBlock) void children_multi_kernel(
   __shared__ __align__(16) uint32_t lds[Q::CPB * M * Q::W];
   const PopDesc d = descs[block_pop[blockIdx.x]];
   children_block(d, node, [&](uint32_t G) __attribute__((always_inline)) {
-    EliteRow er{make_uint4(0, 0, 0, 0), 0u};
-    if (d.ew) er = load_first_elite<M>(d, G);
     const unsigned long long b = child<M, 0, L, false>(d, G, node, lds);
-    if (d.ew) copy_elites<M, false>(d, G, er);
+    // the elites after the child: a row held across it would cost this
+    // kernel's occupancy (it keeps the fitness kind as a run-time choice)
+    if (d.ew) copy_elites<M, false>(d, G, load_first_elite<M>(d, G));
     return b;
   });
 }
