@@ -12,10 +12,9 @@
 //  * count: each tile counts its keys at top - d for d < kPaperBins (LDS
 //    bins) and below that window, and writes for each d its keys at distance
 //    d or more (a suffix sum) and its keys below; top is the previous
-//    selection's T.  T never
-//    increases from one generation to the next (the 2N parents of a
-//    generation carry keys <= the T that selected them), so T lies in
-//    [0, top], and in practice within the window.
+//    selection's T.  T never increases from one generation to the next (the
+//    2N parents of a generation carry keys <= the T that selected them), so
+//    T lies in [0, top], and in practice within the window.
 //  * list: every tile adds the tiles' suffix sums (thread t takes d = t: the
 //    count of keys <= top - d without a scan), finds T and r and the counts of
 //    selected keys below T and equal to T in the tiles before it (two words
