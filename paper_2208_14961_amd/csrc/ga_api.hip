@@ -151,6 +151,10 @@ struct Workspace {
 
 // Graphs kept per workspace: the lanes-per-child candidates of one run shape.
 constexpr size_t kGraphCache = 4;
+// Runs of at least this many chunks measure the lanes-per-child candidates
+// at their start, each over kLanesProbe children launches.
+constexpr uint32_t kExploreMinChunks = 4;
+constexpr uint32_t kLanesProbe = 8;
 
 static hipError_t drop_graphs(Workspace* w) {
   hipError_t e = hipSuccess;
@@ -602,17 +606,16 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     w->graph = exec;
     return GA_OK;
   };
-  // Lanes per child: forced by the config, or measured on this run's own
-  // first chunks (every variant makes the same generations) and remembered
-  // for later runs of the same shape, or, for runs too short to measure,
-  // the tuning table's.
+  // Lanes per child: forced by the config, or measured at the start of the
+  // run and remembered for later runs of the same shape, or, for runs too
+  // short for the measurement to pay, the tuning table's.
   const TuneKey tkey = tune_key(cfg, d);
   const std::vector<uint32_t> cands = lanes_candidates(cfg->m);
   bool explore = false;
   if (!forced_lanes(cfg)) {
     uint32_t known = 0;
     if (tuned_lookup(tkey, &known)) set_lanes(&d, known);
-    else explore = nchunks >= 2 * cands.size() + 1;
+    else explore = nchunks >= kExploreMinChunks;
   }
   uint32_t first = 0;    // chunks already run
   bool finished = false;  // the run ended inside those chunks
@@ -637,55 +640,80 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     }
   }
   if (explore) {
-    // Each candidate: one chunk to settle (a new graph's first launch,
-    // caches), then timed chunks.  With enough chunks the candidates are
-    // timed twice, in the order c1 .. ck ck .. c1, so that a drift of the
-    // generation time over the run (selection work changes as the
-    // population converges) weighs on every candidate alike.
+    // Each candidate's children launch of generation 1, kLanesProbe times in
+    // one captured graph: one untimed replay each, then replays timed in the
+    // order c1 .. ck ck .. c1.  Every launch makes generation 1 from
+    // generation 0 the same way (with elitism it also sets the same
+    // candidate marks), and the first chunk makes it again, so the run's
+    // generations do not depend on the measurement; unlike timing whole
+    // chunks, every candidate is timed on the same work (the selection
+    // launches of later generations change cost as the population
+    // converges).  A selecting mode first makes generation 1's selection,
+    // which the first chunk also makes again.
+    if (!d.ew) {
+      const uint32_t cnt = select_count(cfg);
+      if (table)
+        GA_TRY(launch_perm_table(d, D, chunk, w->perm, w->capture, d.psel != nullptr),
+               "slot table kernel");
+      if (d.psel) {
+        GA_TRY(launch_paper_select(d, 0, d.psel, w->capture), "selection kernels");
+      } else if (cnt > 0) {
+        GA_TRY(launch_select(d, cnt, w->sel, 0, table ? w->perm : nullptr, w->capture),
+               "selection kernels");
+      }
+    }
+    struct ProbeGraphs {
+      std::vector<hipGraphExec_t> g;
+      ~ProbeGraphs() {
+        for (hipGraphExec_t e : g)
+          if (e) (void)hipGraphExecDestroy(e);
+      }
+    } probes;
     const uint32_t nc = (uint32_t)cands.size();
-    const bool twice = nchunks >= 3 * (uint64_t)nc + 1;
-    std::vector<float> total(nc, 0.f);
-    std::vector<uint32_t> timed(nc, 0);
-    const uint32_t visits = twice ? 2 * nc : nc;
-    for (uint32_t k = 0; k < visits && !finished; ++k) {
-      const uint32_t ci = k < nc ? k : 2 * nc - 1 - k;
-      set_lanes(&d, cands[ci]);
-      st = capture(d);
-      if (st != GA_OK) return st;
-      for (int rep = k < nc ? 0 : 1; rep < 2 && !finished; ++rep) {
-        GA_TRY(hipEventRecord(w->ev_t[0], w->capture), "hipEventRecord");
-        GA_TRY(hipGraphLaunch(w->graph, w->capture), "hipGraphLaunch");
-        GA_TRY(hipEventRecord(w->ev_t[1], w->capture), "hipEventRecord");
-        GA_TRY(hipMemcpyAsync(&w->host_state[0], w->state, sizeof(RunState),
-                              hipMemcpyDeviceToHost, w->capture),
-               "hipMemcpyAsync(state)");
-        GA_TRY(hipStreamSynchronize(w->capture), "hipStreamSynchronize");
-        ++first;
-        finished = run_done(w->host_state[0], cfg->max_generations, stop_on_found);
-        if (rep == 1) {
-          float ms = 0;
-          GA_TRY(hipEventElapsedTime(&ms, w->ev_t[0], w->ev_t[1]), "hipEventElapsedTime");
-          total[ci] += ms;
-          ++timed[ci];
-        }
-      }
-    }
-    // the least mean time among the candidates timed (all of them, equally
-    // often, unless the run ended during the measurement)
-    uint32_t best = d.lanes;
-    float best_ms = 0.f;
-    bool any = false;
     for (uint32_t ci = 0; ci < nc; ++ci) {
-      if (!timed[ci]) continue;
-      const float mean = total[ci] / (float)timed[ci];
-      if (!any || mean < best_ms) {
-        best_ms = mean;
-        best = cands[ci];
-        any = true;
-      }
+      PopDesc dc = d;
+      set_lanes(&dc, cands[ci]);
+      hipGraph_t g;
+      GA_TRY(hipStreamBeginCapture(w->capture, hipStreamCaptureModeThreadLocal),
+             "hipStreamBeginCapture");
+      ga_status cs = GA_OK;
+      for (uint32_t r = 0; r < kLanesProbe && cs == GA_OK; ++r)
+        cs = hip_status(launch_children_one(dc, 0, w->capture), "children kernel");
+      hipError_t ce = hipStreamEndCapture(w->capture, &g);
+      if (cs != GA_OK) return cs;
+      GA_TRY(ce, "hipStreamEndCapture");
+      hipGraphExec_t exec = nullptr;
+      const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      GA_TRY(ie, "hipGraphInstantiate");
+      probes.g.push_back(exec);
     }
-    if (!finished) tuned_store(tkey, best);  // a measurement cut short is not kept
-    set_lanes(&d, best);
+    std::vector<float> total(nc, 0.f);
+    for (uint32_t k = 0; k < 3 * nc; ++k) {
+      const uint32_t ci = k < nc ? k : (k < 2 * nc ? k - nc : 3 * nc - 1 - k);
+      if (k < nc) {
+        GA_TRY(hipGraphLaunch(probes.g[ci], w->capture), "hipGraphLaunch");
+        continue;
+      }
+      GA_TRY(hipEventRecord(w->ev_t[0], w->capture), "hipEventRecord");
+      GA_TRY(hipGraphLaunch(probes.g[ci], w->capture), "hipGraphLaunch");
+      GA_TRY(hipEventRecord(w->ev_t[1], w->capture), "hipEventRecord");
+      GA_TRY(hipEventSynchronize(w->ev_t[1]), "hipEventSynchronize");
+      float ms = 0;
+      GA_TRY(hipEventElapsedTime(&ms, w->ev_t[0], w->ev_t[1]), "hipEventElapsedTime");
+      total[ci] += ms;
+    }
+    uint32_t best = 0;
+    for (uint32_t ci = 1; ci < nc; ++ci)
+      if (total[ci] < total[best]) best = ci;
+    // launches of a run that is already over (a solution in generation 0
+    // with stop-on-found) return at once: nothing was measured
+    GA_TRY(hipMemcpyAsync(&w->host_state[0], w->state, sizeof(RunState), hipMemcpyDeviceToHost,
+                          w->capture),
+           "hipMemcpyAsync(state)");
+    GA_TRY(hipStreamSynchronize(w->capture), "hipStreamSynchronize");
+    if (!run_done(w->host_state[0], 1, stop_on_found)) tuned_store(tkey, cands[best]);
+    set_lanes(&d, cands[best]);
   }
   if (first < nchunks && !finished) {
     st = capture(d);

@@ -532,26 +532,30 @@ def test_run_paper_study_cells(m, nc, nr, kind, gens):
 
 
 @pytest.mark.parametrize("cfg", [
-    # each candidate timed once (fewer than 3 chunks per candidate + 1)
     ga.Config(m=20, n=1500, seed=31, max_generations=400, flags=0),
     ga.Config(m=40, n=400, seed=32, elite=5, fitness=ga.FIT_ABS, max_generations=300, flags=0),
-    # each timed twice, in the order c1 .. ck ck .. c1
     ga.Config(m=20, n=1500, seed=33, max_generations=700, flags=0),
     ga.Config(m=40, n=400, seed=34, elite=5, fitness=ga.FIT_ABS, max_generations=450, flags=0),
+    # paper mode: generation 1's selection made before the measurement and again by the run
     ga.Config(m=16, n=2000, seed=35, selection=ga.SEL_PAPER, fitness=ga.FIT_F1,
               xo_threshold=1 << 32, mut_threshold=1 << 32, nc=2, nr=2, max_generations=650,
               flags=0),
-    # a solution found while the candidates are still being timed
+    # a solution found in the first chunk, after the measurement
     ga.Config(m=8, n=1024, seed=36, max_generations=700),
+    # the shortest run that measures (four chunks)
+    ga.Config(m=12, n=600, seed=37, elite=3, fitness=ga.FIT_NNZ, max_generations=193, flags=0),
 ])
 def test_run_tunes_lanes_inside_the_run(cfg):
-    """A run long enough to measure every lanes-per-child variant on its own
-    first chunks, then one that reuses the measured choice: both equal the
-    oracle's run."""
+    """A run long enough to time every lanes-per-child variant on its own
+    generation 1 before its chunks, then one that reuses the measured choice:
+    both equal the oracle's run, and the choice is one of the variants."""
     torch_cuda()
     announce("run tuned twice", cfg)
     _same_run(cfg)
+    lanes = ga.ga_tuned_lanes(cfg)
+    assert lanes in ((2, 4, 8) if cfg.m <= 32 else (4, 8) if cfg.m <= 64 else (8, 16)), lanes
     _same_run(cfg)
+    assert ga.ga_tuned_lanes(cfg) == lanes
 
 
 # --------------------------------------------------------------------------
