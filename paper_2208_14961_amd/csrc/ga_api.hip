@@ -132,11 +132,10 @@ struct Workspace {
   PaperWork* pw = nullptr;         // paper mode up to kPaperTileMaxN: the tile selection
   uint32_t* psel = nullptr;        // and its list of selected indices (psel_cap entries)
   uint64_t psel_cap = 0;
-  // elitism: the next elites' sources, the candidate bitmap and the
-  // selection's item list, for populations up to elite_cap
+  // elitism: the next elites' sources, the candidate lists and the
+  // selection's scratch, for populations up to elite_cap
   EliteWork* ew = nullptr;
-  uint32_t* emark = nullptr;
-  uint32_t* eitems = nullptr;      // slots of long candidate lists: elite_cap words
+  uint32_t* earea = nullptr;       // candidate lists and scratch (elite_area_words)
   uint64_t elite_cap = 0;
   // graphs of one chunk of generations, each valid for its key (the launch
   // descriptor, config and table); the last used last.  `graph` is the one
@@ -303,7 +302,7 @@ static ga_status enqueue_generation(const ga_config* c, const PopDesc& d,
                                     const uint32_t* slots, hipStream_t s) {
   if (d.ew) {
     GA_TRY(launch_children_one(d, node, s), "children kernel");
-    GA_TRY(launch_elite_select(d, node + 1, w->eitems, s), "elite selection kernel");
+    GA_TRY(launch_elite_select(d, node + 1, s), "elite selection kernel");
     return GA_OK;
   }
   if (d.psel) {
@@ -528,21 +527,17 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
   if (elites && w->elite_cap < cfg->n) {
     GA_TRY(hipStreamSynchronize(w->capture), "hipStreamSynchronize");
     GA_TRY(drop_graphs(w), "hipGraphExecDestroy");
-    if (w->emark) GA_TRY(hipFree(w->emark), "hipFree(candidate bitmap)");
-    if (w->eitems) GA_TRY(hipFree(w->eitems), "hipFree(candidate list)");
-    w->emark = nullptr;
-    w->eitems = nullptr;
+    if (w->earea) GA_TRY(hipFree(w->earea), "hipFree(candidate lists)");
+    w->earea = nullptr;
     w->elite_cap = 0;
     if (!w->ew) GA_TRY(hipMalloc(&w->ew, sizeof(EliteWork)), "hipMalloc(elites)");
-    GA_TRY(hipMalloc(&w->emark, ((size_t)cfg->n + 31) / 32 * sizeof(uint32_t)),
-           "hipMalloc(candidate bitmap)");
-    GA_TRY(hipMalloc(&w->eitems, (size_t)cfg->n * sizeof(uint32_t)), "hipMalloc(candidate list)");
+    GA_TRY(hipMalloc(&w->earea, elite_area_words(cfg->n) * sizeof(uint32_t)),
+           "hipMalloc(candidate lists)");
     w->elite_cap = cfg->n;
   }
   if (elites) {
     d.ew = w->ew;
-    d.mark = w->emark;
-    d.eitems = w->eitems;
+    set_elite_area(&d, w->earea);
   }
   // Paper mode up to kPaperOneBlockMaxN: one block selects (indices and
   // keys into psel) and the children launch gathers the parents through the
@@ -624,11 +619,10 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     GA_TRY(hipEventRecord(w->ev[2], s), "hipEventRecord");
     GA_TRY(hipStreamWaitEvent(w->capture, w->ev[2], 0), "hipStreamWaitEvent");
     // the first generation's elites, from the whole initial population, and
-    // a clear candidate bitmap
+    // empty candidate lists
     if (elites) {
-      GA_TRY(hipMemsetAsync(w->emark, 0, ((size_t)cfg->n + 31) / 32 * sizeof(uint32_t),
-                            w->capture),
-             "hipMemsetAsync(candidate bitmap)");
+      GA_TRY(hipMemsetAsync(d.ecount, 0, kEliteLists * sizeof(uint32_t), w->capture),
+             "hipMemsetAsync(candidate lists)");
       GA_TRY(launch_select(d, cfg->elite, w->sel, 0, nullptr, w->capture, w->ew->src,
                            &w->ew->kstar),
              "selection kernels");
@@ -673,6 +667,7 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     for (uint32_t ci = 0; ci < nc; ++ci) {
       PopDesc dc = d;
       set_lanes(&dc, cands[ci]);
+      dc.ecount = nullptr;  // the timed launches list no candidates
       hipGraph_t g;
       GA_TRY(hipStreamBeginCapture(w->capture, hipStreamCaptureModeThreadLocal),
              "hipStreamBeginCapture");

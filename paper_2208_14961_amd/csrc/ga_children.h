@@ -473,8 +473,23 @@ __device__ __forceinline__ unsigned long long child(const PopDesc& d, uint32_t G
   }
   if (l == 0) store_key<NT>(kout + dst, key);
   // elitism in ga_run: a child below the largest elite key may be among the
-  // next elites (rare: one atomic per such child)
-  if (d.mark && l == 0 && key < d.ew->kstar) atomicOr(&d.mark[dst >> 5], 1u << (dst & 31u));
+  // next elites; the block's such children go to its candidate list, with
+  // one atomic for all of them
+  if (d.ecount) {
+    const bool cand = l == 0 && key < d.ew->kstar;
+    const unsigned long long bal = __ballot(cand);
+    if (bal) {
+      const uint32_t list = (blockIdx.x - d.block_begin) % kEliteLists;
+      const int leader = __ffsll((long long)bal) - 1;
+      uint32_t base = 0;
+      if ((int)lane == leader) base = atomicAdd(&d.ecount[list], (uint32_t)__popcll(bal));
+      base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+      if (cand) {
+        const uint32_t rank = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+        d.elist[(size_t)list * d.ecap + base + rank] = make_uint2(dst, key);
+      }
+    }
+  }
   return ((unsigned long long)key << 32) | dst;
 }
 

@@ -71,8 +71,9 @@ struct SelWork;
 // slot) of generation G - 1, in slots 0 .. e-1 of G, so they precede every
 // child on ties: the e smallest of G are among those elites and the
 // children whose key is below kstar, the largest elite key.  The children
-// launch of G copies the elites (src) and marks such children in a bitmap;
-// one single-block launch then picks the next elites from that short list.
+// launch of G copies the elites (src) and appends such children to short
+// candidate lists; one single-block launch then picks the next elites from
+// the elites and those lists.
 struct EliteWork {
   uint32_t kstar;            // largest key among the elites of the generation
                              // the next children launch makes
@@ -98,6 +99,23 @@ struct PaperWork {
                                                   // d <= top - key < kPaperBins;
                                                   // last: its keys below that window
 };
+
+// The candidate lists of an elitist run: a child below the largest elite key
+// is appended, as (slot, key), to list (its block's index in the population)
+// mod kEliteLists with one atomic per block.  A block holds at most 32
+// children, so a list receives at most ceil(n / kEliteLists) + 33 entries.
+// The area holds the lists' counts, their entries (list j from entry
+// j * elite_list_cap(n)), then the selection's scratch for lists too long
+// for its LDS: a bitmap and a prefix count per 32 slots, the items' keys
+// and their slots (n each).
+constexpr uint32_t kEliteLists = 256;
+__host__ __device__ inline uint32_t elite_list_cap(uint32_t n) {
+  return (n + kEliteLists - 1) / kEliteLists + 33;
+}
+inline size_t elite_area_words(uint32_t n) {
+  const size_t nw = ((size_t)n + 31) / 32;
+  return kEliteLists + (size_t)kEliteLists * elite_list_cap(n) * 2 + 2 * nw + 2 * (size_t)n;
+}
 
 struct PopDesc {
   uint32_t* pop_a;
@@ -125,9 +143,11 @@ struct PopDesc {
   uint32_t* slots;       // batched and served paper-mode runs: kBatchTableRows rows of
                          // slot permutations for a chunk (null: walked inline)
   EliteWork* ew;         // ga_run with elitism: the children launch copies the elites
-                         // and marks candidates (null: elites copied by the selection)
-  uint32_t* mark;        // with ew: bitmap over slots, a child below ew->kstar
-  uint32_t* eitems;      // with ew: n words, slots of candidate lists past the LDS
+                         // and appends candidates (null: elites copied by the selection)
+  uint32_t* ecount;      // with ew: the kEliteLists candidate counts (see elite_list_cap)
+  uint2* elist;          // with ew: the candidate lists, list j from entry j * ecap
+  uint32_t* escratch;    // with ew: the selection's scratch for long lists
+  uint32_t ecap;         // with ew: entries per candidate list
   PaperWork* pw;          // ga_run paper mode up to kPaperTileMaxN: the tile
                          // selection's work area
   uint32_t* psel;        // with pw: the selected indices of generation G - 1 in
@@ -185,12 +205,18 @@ hipError_t launch_perm_table(const PopDesc& d, uint32_t count, uint32_t nodes,
                              uint32_t* out, hipStream_t s, bool forward = false);
 // ga_run with elitism: the elites of generation gen_base + node + 1 of d
 // chosen from generation gen_base + node (see EliteWork), from its elites
-// and its marked children.  item_slot: n entries of scratch.  (The first
-// generation's come from launch_select with src_out.)
-hipError_t launch_elite_select(const PopDesc& d, uint32_t node, uint32_t* item_slot,
-                               hipStream_t s);
-// The same for several runs in one launch (block b: run descs[runs[b]], its
-// d.eitems as the scratch).
+// and its listed children.  (The first generation's come from launch_select
+// with src_out.)
+hipError_t launch_elite_select(const PopDesc& d, uint32_t node, hipStream_t s);
+// Points d's candidate lists and scratch into an area of
+// elite_area_words(d->n) words.
+inline void set_elite_area(PopDesc* d, uint32_t* area) {
+  d->ecap = elite_list_cap(d->n);
+  d->ecount = area;
+  d->elist = reinterpret_cast<uint2*>(area + kEliteLists);
+  d->escratch = area + kEliteLists + (size_t)kEliteLists * d->ecap * 2;
+}
+// The same for several runs in one launch (block b: run descs[runs[b]]).
 hipError_t launch_elite_select_multi(const PopDesc* descs_dev, const uint32_t* runs,
                                      uint32_t count, uint32_t node, hipStream_t s);
 // Paper mode up to kPaperTileMaxN, parents of generation gen_base + node + 1
@@ -265,9 +291,8 @@ struct RunBuffers {
   uint32_t* slots = nullptr;  // paper-mode runs: a chunk's slot table
   PaperWork* pw = nullptr;    // paper-mode runs up to kPaperTileMaxN with a table:
   uint32_t* psel = nullptr;   // the tile selection and its list (then slots holds pi)
-  EliteWork* ew = nullptr;    // elitist runs: elites from a candidate list, as in
-  uint32_t* emark = nullptr;  // ga_run (the candidate bitmap and the long-list
-  uint32_t* eitems = nullptr; // slots)
+  EliteWork* ew = nullptr;    // elitist runs: elites from candidate lists, as in
+  uint32_t* earea = nullptr;  // ga_run (elite_area_words(n) words)
   void* base = nullptr;   // single allocation holding all of them
 };
 size_t run_bytes(const ga_config* c);

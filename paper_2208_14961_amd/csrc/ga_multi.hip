@@ -41,11 +41,10 @@ static size_t tile_bytes(const ga_config* c) {
 }
 
 // Elitist runs choose their elites as ga_run does: from the previous elites
-// and the children marked below the largest elite key (ga_elite.hip).
+// and the children listed below the largest elite key (ga_elite.hip).
 static size_t elite_bytes(const ga_config* c) {
   if (c->selection != GA_SEL_TOURNAMENT || c->elite == 0) return 0;
-  return align256(sizeof(EliteWork)) + align256(((size_t)c->n + 31) / 32 * 4) +
-         align256((size_t)c->n * 4);
+  return align256(sizeof(EliteWork)) + align256(elite_area_words(c->n) * 4);
 }
 
 size_t run_bytes(const ga_config* c) {
@@ -78,8 +77,7 @@ ga_status alloc_run(const ga_config* c, RunBuffers* b) {
     char* t = base + 2 * pop + 2 * keys + sel + table_bytes(c) + tile_bytes(c);
     b->ew = reinterpret_cast<EliteWork*>(t);
     t += align256(sizeof(EliteWork));
-    b->emark = reinterpret_cast<uint32_t*>(t);
-    b->eitems = reinterpret_cast<uint32_t*>(t + align256(((size_t)c->n + 31) / 32 * 4));
+    b->earea = reinterpret_cast<uint32_t*>(t);
   }
   return GA_OK;
 }
@@ -96,8 +94,7 @@ PopDesc run_desc(const ga_config* c, const RunBuffers& b, RunState* st) {
   }
   if (b.ew) {
     d.ew = b.ew;
-    d.mark = b.emark;
-    d.eitems = b.eitems;
+    set_elite_area(&d, b.earea);
   }
   return d;
 }
@@ -312,11 +309,11 @@ static ga_status start_run(const ga_config* c, const RunBuffers& b,
   if (b.sel) GA_TRY(hipMemsetAsync(b.sel, 0, sizeof(SelWork), s), "hipMemsetAsync(selection)");
   // the tile selection: no threshold yet
   if (b.pw) GA_TRY(hipMemsetAsync(b.pw->T, 0xff, sizeof(b.pw->T), s), "hipMemsetAsync(selection)");
-  // candidate-list elitism: a clear bitmap (the elites of generation 1 are
+  // candidate-list elitism: empty lists (the elites of generation 1 are
   // chosen below, once the initial keys exist)
   if (b.ew)
-    GA_TRY(hipMemsetAsync(b.emark, 0, ((size_t)c->n + 31) / 32 * sizeof(uint32_t), s),
-           "hipMemsetAsync(candidate bitmap)");
+    GA_TRY(hipMemsetAsync(b.earea, 0, kEliteLists * sizeof(uint32_t), s),
+           "hipMemsetAsync(candidate lists)");
   GA_TRY(launch_reset_state(st, s), "state kernel");
   GA_TRY(launch_init(c, b.pop_a, s), "init kernel");
   GA_TRY(launch_fitness(c, b.pop_a, b.keys_a, nullptr, st, s), "fitness kernel");

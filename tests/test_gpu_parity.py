@@ -506,6 +506,14 @@ def test_run_parity(cfg):
     ga.Config(m=44, n=2000, seed=6, elite=31, fitness=ga.FIT_F1, max_generations=66, flags=0),
     ga.Config(m=68, n=900, seed=7, elite=90, fitness=ga.FIT_F2, max_generations=20, flags=0),
     ga.Config(m=100, n=500, seed=8, elite=65, fitness=ga.FIT_ABS, max_generations=10, flags=0),
+    # more items than the selection holds in LDS (10,240): its lists and bitmap in global memory
+    ga.Config(m=12, n=30000, seed=9, elite=10000, fitness=ga.FIT_ABS, max_generations=12, flags=0),
+    # more slots than its LDS bitmap covers (262,144)
+    ga.Config(m=8, n=300000, seed=10, elite=50, max_generations=8, flags=0),
+    # half the population elite, 8-way tournaments at m = 72: in generation 1
+    # the threshold lies 4624 below the largest elite key, under the
+    # selection's 4096-wide window (checked with the oracle)
+    ga.Config(m=72, n=800, seed=11, elite=400, tournament_k=8, max_generations=6, flags=0),
 ])
 def test_run_elitism(cfg):
     """Whole elitist runs through ga_run, whose elites come from the previous
