@@ -10,8 +10,8 @@ per generation plus the initial population), the roofline of the fused
 children kernel, the oracle's CPU throughput (all cores and one thread),
 the time-to-solve of the m = 8, n = 1,024 plain GA over 32 seeds, and
 summaries of the batched workload (24 runs against one ga_run each) and of
-the served workload (the Poisson stream of 2,000 requests, then its first
-200 requests at once against one ga_run each).
+the server (the served stream's first 200 requests submitted at once,
+against one ga_run each).
 
 --workload batched: 24 runs in one batched launch per generation against
 the same 24 runs one after another.
@@ -487,7 +487,12 @@ def bench_default(args):
     if not args.no_multi:
         out["batched"] = batched_leg(steps=2)
         print("default: batched leg done", file=sys.stderr, flush=True)
-        out["served"] = served_leg(args.requests, args.saturated)
+        # the Poisson stream (served_leg, --workload served) is not part of
+        # the default line: one run of it ended in a host segmentation fault
+        # whose cause has not been found; the server is measured here on
+        # the stream's first requests submitted at once
+        out["served"] = served_saturated(workload_served(count=args.saturated)[0])
+        print("default: served leg done", file=sys.stderr, flush=True)
     return out
 
 
@@ -637,7 +642,9 @@ def served_saturated(cfgs):
     ids = [srv.submit(c) for c in cfgs]
     served = [srv.wait(i) for i in ids]
     dt_s = time.perf_counter() - t
+    lat = [srv.latency(i) for i in ids]
     srv.close()
+    solved = [l for l, r in zip(lat, served) if r["found"]]
     print(f"served: saturated leg, {len(cfgs)} requests at once in {dt_s:.2f} s",
           file=sys.stderr, flush=True)
     bufs = [buffers(c) for c in cfgs]
@@ -652,8 +659,16 @@ def served_saturated(cfgs):
     gens = sum(r["generation"] for r in served)
     evals = sum(c.n * (r["generation"] + 1) for c, r in zip(cfgs, served))
     return {"requests": len(cfgs), "generations": gens,
+            "workload": f"the first {len(cfgs)} requests of the served stream (m in 8..64 step 4, "
+                        "n in [1000,50000], budget 2000 generations, stop on found) submitted "
+                        "at once to a server with a 200 GB admission budget",
             "server": {"seconds": dt_s, "generations_per_s": gens / dt_s,
-                       "evals_per_s": evals / dt_s},
+                       "evals_per_s": evals / dt_s, "requests_per_s": len(cfgs) / dt_s,
+                       "solved": len(solved), "solve_rate": len(solved) / len(cfgs),
+                       "time_to_first_hadamard": {"p50_s": percentile(solved, 50),
+                                                  "p99_s": percentile(solved, 99)},
+                       "time_to_retire": {"p50_s": percentile(lat, 50),
+                                          "p99_s": percentile(lat, 99)}},
             "plain": {"seconds": dt_p, "generations_per_s": gens / dt_p,
                       "evals_per_s": evals / dt_p},
             "speedup_vs_plain": dt_p / dt_s,

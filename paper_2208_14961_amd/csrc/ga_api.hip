@@ -151,9 +151,11 @@ struct Workspace {
 // Graphs kept per workspace: the lanes-per-child candidates of one run shape.
 constexpr size_t kGraphCache = 4;
 // Runs of at least this many chunks measure the lanes-per-child candidates
-// at their start, each over kLanesProbe children launches.
+// at their start: a graph of kLanesProbe children launches per candidate,
+// replayed once untimed and kLanesRounds times timed.
 constexpr uint32_t kExploreMinChunks = 4;
-constexpr uint32_t kLanesProbe = 8;
+constexpr uint32_t kLanesProbe = 16;
+constexpr uint32_t kLanesRounds = 4;
 
 static hipError_t drop_graphs(Workspace* w) {
   hipError_t e = hipSuccess;
@@ -635,8 +637,10 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
   }
   if (explore) {
     // Each candidate's children launch of generation 1, kLanesProbe times in
-    // one captured graph: one untimed replay each, then replays timed in the
-    // order c1 .. ck ck .. c1.  Every launch makes generation 1 from
+    // one captured graph: one untimed replay each, then kLanesRounds timed
+    // rounds in the order c1 .. ck, ck .. c1, c1 .. ck, ...; each candidate
+    // counts its fastest replay (interference only adds time).  Every
+    // launch makes generation 1 from
     // generation 0 the same way (with elitism it also sets the same
     // candidate marks), and the first chunk makes it again, so the run's
     // generations do not depend on the measurement; unlike timing whole
@@ -683,24 +687,23 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
       GA_TRY(ie, "hipGraphInstantiate");
       probes.g.push_back(exec);
     }
-    std::vector<float> total(nc, 0.f);
-    for (uint32_t k = 0; k < 3 * nc; ++k) {
-      const uint32_t ci = k < nc ? k : (k < 2 * nc ? k - nc : 3 * nc - 1 - k);
-      if (k < nc) {
-        GA_TRY(hipGraphLaunch(probes.g[ci], w->capture), "hipGraphLaunch");
-        continue;
-      }
+    for (uint32_t ci = 0; ci < nc; ++ci)
+      GA_TRY(hipGraphLaunch(probes.g[ci], w->capture), "hipGraphLaunch");
+    std::vector<float> fastest(nc, 0.f);
+    for (uint32_t k = 0; k < kLanesRounds * nc; ++k) {
+      const uint32_t round = k / nc, pos = k % nc;
+      const uint32_t ci = (round & 1u) ? nc - 1 - pos : pos;
       GA_TRY(hipEventRecord(w->ev_t[0], w->capture), "hipEventRecord");
       GA_TRY(hipGraphLaunch(probes.g[ci], w->capture), "hipGraphLaunch");
       GA_TRY(hipEventRecord(w->ev_t[1], w->capture), "hipEventRecord");
       GA_TRY(hipEventSynchronize(w->ev_t[1]), "hipEventSynchronize");
       float ms = 0;
       GA_TRY(hipEventElapsedTime(&ms, w->ev_t[0], w->ev_t[1]), "hipEventElapsedTime");
-      total[ci] += ms;
+      if (round == 0 || ms < fastest[ci]) fastest[ci] = ms;
     }
     uint32_t best = 0;
     for (uint32_t ci = 1; ci < nc; ++ci)
-      if (total[ci] < total[best]) best = ci;
+      if (fastest[ci] < fastest[best]) best = ci;
     // launches of a run that is already over (a solution in generation 0
     // with stop-on-found) return at once: nothing was measured
     GA_TRY(hipMemcpyAsync(&w->host_state[0], w->state, sizeof(RunState), hipMemcpyDeviceToHost,
