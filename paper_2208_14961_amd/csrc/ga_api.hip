@@ -614,8 +614,6 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     if (tuned_lookup(tkey, &known)) set_lanes(&d, known);
     else explore = nchunks >= kExploreMinChunks;
   }
-  uint32_t first = 0;    // chunks already run
-  bool finished = false;  // the run ended inside those chunks
   if (nchunks > 0) {
     // the capture stream starts after the work already enqueued on s
     GA_TRY(hipEventRecord(w->ev[2], s), "hipEventRecord");
@@ -640,14 +638,13 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     // one captured graph: one untimed replay each, then kLanesRounds timed
     // rounds in the order c1 .. ck, ck .. c1, c1 .. ck, ...; each candidate
     // counts its fastest replay (interference only adds time).  Every
-    // launch makes generation 1 from
-    // generation 0 the same way (with elitism it also sets the same
-    // candidate marks), and the first chunk makes it again, so the run's
-    // generations do not depend on the measurement; unlike timing whole
-    // chunks, every candidate is timed on the same work (the selection
-    // launches of later generations change cost as the population
-    // converges).  A selecting mode first makes generation 1's selection,
-    // which the first chunk also makes again.
+    // launch makes generation 1 from generation 0 the same way (with
+    // elitism the timed launches list no candidates), and the first chunk
+    // makes it again, so the run's generations do not depend on the
+    // measurement; unlike timing whole chunks, every candidate is timed on
+    // the same work (the selection launches of later generations change
+    // cost as the population converges).  A selecting mode first makes
+    // generation 1's selection, which the first chunk also makes again.
     if (!d.ew) {
       const uint32_t cnt = select_count(cfg);
       if (table)
@@ -713,7 +710,7 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     if (!run_done(w->host_state[0], 1, stop_on_found)) tuned_store(tkey, cands[best]);
     set_lanes(&d, cands[best]);
   }
-  if (first < nchunks && !finished) {
+  if (nchunks > 0) {
     st = capture(d);
     if (st != GA_OK) return st;
     // the capture stream starts after the work already enqueued on s
@@ -728,9 +725,9 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
       GA_TRY(hipEventRecord(w->ev[k & 1], w->capture), "hipEventRecord");
       return GA_OK;
     };
-    st = launch_chunk(first);
+    st = launch_chunk(0);
     if (st != GA_OK) return st;
-    for (uint32_t k = first; k < nchunks; ++k) {
+    for (uint32_t k = 0; k < nchunks; ++k) {
       if (k + 1 < nchunks) {
         st = launch_chunk(k + 1);
         if (st != GA_OK) return st;
@@ -751,10 +748,8 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
                                ? w->host_state[0] : w->host_state[1];
       uint32_t made = std::min(cfg->max_generations, hs.gen_base);
       if (stop_on_found && hs.found_gen < made) made = hs.found_gen;
-      const uint32_t before = (uint32_t)std::min<uint64_t>(cfg->max_generations,
-                                                           (uint64_t)first * chunk);
       g_timing.total_ms += ms;
-      g_timing.gens += made > before ? made - before : 0;
+      g_timing.gens += made;
     }
   }
   if (nchunks > 0) {

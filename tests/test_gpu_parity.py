@@ -658,7 +658,8 @@ def test_run_batch_elitist_runs_share_elite_launch():
     """Several elitist runs of one order choose their elites from candidate
     lists in one shared launch per generation (each block one run): ties
     (m = 4 keys take three values), almost every slot an elite, one elite,
-    kinds with one- and two-level key ranges; each equals the oracle's run."""
+    kinds with one- and two-level key ranges, a run whose items exceed the
+    LDS; each equals the oracle's run."""
     torch_cuda()
     cfgs = [
         ga.Config(m=4, n=1000, seed=81, elite=300, max_generations=40, flags=0),
@@ -666,6 +667,9 @@ def test_run_batch_elitist_runs_share_elite_launch():
         ga.Config(m=20, n=5000, seed=83, elite=1, fitness=ga.FIT_NNZ, max_generations=60),
         ga.Config(m=20, n=3001, seed=84, elite=700, fitness=ga.FIT_ABS, max_generations=50, flags=0),
         ga.Config(m=20, n=20000, seed=85, elite=200, fitness=ga.FIT_SQ_PLUS_NNZ, max_generations=40,
+                  flags=0),
+        # more items than the selection holds in LDS: its scratch in global memory
+        ga.Config(m=20, n=24000, seed=88, elite=11000, fitness=ga.FIT_ABS, max_generations=10,
                   flags=0),
         ga.Config(m=20, n=900, seed=86, max_generations=30),
         ga.Config(m=20, n=800, seed=87, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
