@@ -210,6 +210,11 @@ __device__ __forceinline__ uint32_t feistel_half_bits(uint32_t D) {
   while ((1ull << (2 * h)) < (uint64_t)D) ++h;
   return h;
 }
+static uint32_t feistel_half_bits_host(uint32_t D) {
+  uint32_t h = 1;
+  while ((1ull << (2 * h)) < (uint64_t)D) ++h;
+  return h;
+}
 
 // One inverse evaluation of the eight-round network on 2h bits.
 __device__ __forceinline__ uint32_t feistel_inverse(uint64_t seed, uint32_t G,
@@ -254,73 +259,105 @@ __device__ uint32_t perm_inverse(uint64_t seed, uint32_t G, uint32_t D,
 }
 
 // The slot pi^-1(rho) of every rank rho < D, for the generations of launches
-// 0 .. nodes-1 of a chunk (row `node` for generation gen_base + node + 1).
-// Each element is a serial cycle walk of eight-round Feistel evaluations, so
-// the whole chunk's rows are computed in one wide launch where the scatter
-// of one generation would have a single element per lane.
-// The walks have very uneven lengths (about 3.3 network evaluations on
-// average at 2N = 20,000, up to a dozen in a wave of 64), so each wave owns
-// a pool of kPermPerWave elements and a lane that ends a walk takes the
-// next element of the pool: the wave runs for about the pool's total walk
-// length over 64 plus one walk, not 64 times its longest walk.  Element t
-// (row t / D, rank t % D) gets exactly perm_inverse's value; with FWD, row
-// t / D holds instead pi(s) of every parent slot s = t % D (the forward
-// network, walked the same way).
-constexpr uint32_t kPermPerWave = 512;
+// 0 .. nodes-1 of a chunk (row `node` for generation gen_base + node + 1);
+// with FWD, row r holds instead pi(s) of every parent slot s (the forward
+// network).  Each element is a serial cycle walk of eight-round Feistel
+// evaluations (about 3.3 on average at 2N = 20,000).  Within one generation
+// each round function has only 2^h inputs, so a block first tabulates the
+// eight functions of its row in LDS (the two Philox blocks of every input
+// value: the same words the network's evaluations draw), and the walks then
+// take one table read per round instead of one Philox block.  Element
+// (row, e) gets exactly perm_inverse's value (feistel_forward's walk with
+// FWD).  The walks have uneven lengths (up to a dozen evaluations in a wave
+// of 64), so each wave owns a pool of its block's elements and a lane that
+// ends a walk takes the next element of the pool.
+constexpr uint32_t kPermPerBlock = 2048;  // elements of a row per block
 
 template <bool FWD>
 __global__ __launch_bounds__(kBlock) void perm_table_kernel(const RunState* st,
                                                             uint64_t seed, uint32_t D,
-                                                            uint32_t nodes,
+                                                            uint32_t bpr,
                                                             uint32_t* __restrict__ out) {
-  const uint64_t total = (uint64_t)D * nodes;
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint64_t begin = wave * kPermPerWave;
-  if (begin >= total) return;  // uniform over the wave
-  const uint64_t end = min(begin + kPermPerWave, total);
-  const uint32_t gb = st->gen_base, h = feistel_half_bits(D);
+  extern __shared__ uint16_t ftab[];  // round r's function at ftab[r * H + v]
+  const uint32_t row = blockIdx.x / bpr, part = blockIdx.x % bpr;
+  const uint32_t h = feistel_half_bits(D), H = 1u << h, mask = H - 1u;
+  const uint32_t G = st->gen_base + row + 1;
+  for (uint32_t v = threadIdx.x; v < 2 * H; v += kBlock) {
+    const uint32_t in = v >> 1, b = v & 1u;  // rounds 4b .. 4b + 3
+    const U4 u = draw_block(seed, kStreamPerm, G, in, b);
+    ftab[(4 * b + 0) * H + in] = (uint16_t)(u.x & mask);
+    ftab[(4 * b + 1) * H + in] = (uint16_t)(u.y & mask);
+    ftab[(4 * b + 2) * H + in] = (uint16_t)(u.z & mask);
+    ftab[(4 * b + 3) * H + in] = (uint16_t)(u.w & mask);
+  }
+  __syncthreads();
+  // this block's elements of the row, then this wave's pool of them
+  const uint32_t per_block = (D + bpr - 1) / bpr;
+  const uint32_t b0 = min(D, part * per_block), b1 = min(D, b0 + per_block);
+  constexpr uint32_t kWaves = kBlock / 64;
+  const uint32_t wv = threadIdx.x >> 6, per_wave = (b1 - b0 + kWaves - 1) / kWaves;
+  const uint32_t begin = min(b1, b0 + wv * per_wave), end = min(b1, begin + per_wave);
+  if (begin >= end) return;  // uniform over the wave
+  uint32_t* orow = out + (size_t)row * D;
   const uint64_t limit = 1ull << (2 * h);
+  const uint32_t lane = threadIdx.x & 63u;
   const unsigned long long below = (1ull << lane) - 1ull;  // lanes before this one
-  uint64_t next = begin + 64;  // first element not yet taken (same in every lane)
-  uint64_t e = begin + lane;   // this lane's element
+  uint32_t next = begin + 64;  // first element not yet taken (same in every lane)
+  uint32_t e = begin + lane;   // this lane's element
   bool busy = e < end;
-  uint32_t x = busy ? (uint32_t)(e % D) : 0u, G = busy ? gb + (uint32_t)(e / D) + 1 : 0u;
+  uint32_t x = busy ? e : 0u;
   uint64_t it = 0;
   while (__ballot(busy) != 0ull || next < end) {
     if (busy) {
-      x = FWD ? feistel_forward(seed, G, h, x) : feistel_inverse(seed, G, h, x);
+      uint32_t L = x >> h, R = x & mask;
+      if (FWD) {
+#pragma unroll
+        for (uint32_t r = 0; r < 8; ++r) {
+          const uint32_t nr = L ^ ftab[r * H + R];
+          L = R;
+          R = nr;
+        }
+      } else {
+#pragma unroll
+        for (int r = 7; r >= 0; --r) {
+          const uint32_t nl = R ^ ftab[(uint32_t)r * H + L];
+          R = L;
+          L = nl;
+        }
+      }
+      x = (L << h) | R;
       if (x < D || ++it == limit) {
-        out[e] = x;
+        orow[e] = x;
         busy = false;
       }
     }
     const unsigned long long idle = __ballot(!busy);
     if (!busy) {  // take the next element of the pool, in lane order
-      const uint64_t mine = next + (uint64_t)__popcll(idle & below);
+      const uint32_t mine = next + (uint32_t)__popcll(idle & below);
       if (mine < end) {
         e = mine;
-        x = (uint32_t)(e % D);
-        G = gb + (uint32_t)(e / D) + 1;
+        x = e;
         it = 0;
         busy = true;
       }
     }
-    next += (uint64_t)__popcll(idle);
+    next += (uint32_t)__popcll(idle);
   }
 }
 
 hipError_t launch_perm_table(const PopDesc& d, uint32_t count, uint32_t nodes,
                              uint32_t* out, hipStream_t s, bool forward) {
-  const uint64_t total = (uint64_t)count * nodes;
-  const uint64_t waves = (total + kPermPerWave - 1) / kPermPerWave;
-  const dim3 grid(cdiv(waves * 64, kBlock)), block(kBlock);
+  if (count == 0 || nodes == 0) return hipSuccess;
+  const uint32_t bpr = (count + kPermPerBlock - 1) / kPermPerBlock;
+  const uint32_t H = 1u << feistel_half_bits_host(count);
+  const size_t lds = (size_t)8 * H * sizeof(uint16_t);
+  const dim3 grid(nodes * bpr), block(kBlock);
   if (forward)
-    hipLaunchKernelGGL(perm_table_kernel<true>, grid, block, 0, s, d.state, d.seed, count,
-                       nodes, out);
+    hipLaunchKernelGGL(perm_table_kernel<true>, grid, block, lds, s, d.state, d.seed, count, bpr,
+                       out);
   else
-    hipLaunchKernelGGL(perm_table_kernel<false>, grid, block, 0, s, d.state, d.seed, count,
-                       nodes, out);
+    hipLaunchKernelGGL(perm_table_kernel<false>, grid, block, lds, s, d.state, d.seed, count,
+                       bpr, out);
   return hipGetLastError();
 }
 
