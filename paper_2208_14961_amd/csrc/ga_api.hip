@@ -127,6 +127,7 @@ struct Workspace {
   hipStream_t capture = nullptr;   // stream the generation graphs run on
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   hipEvent_t ev_t[2] = {nullptr, nullptr};  // timing of tuning chunks
+  std::vector<hipEvent_t> ev_probe;  // around each timed children launch of the lanes measurement
   uint32_t* perm = nullptr;        // paper mode: a chunk's slot table
   uint64_t perm_cap = 0;           // its entries
   PaperWork* pw = nullptr;         // paper mode up to kPaperTileMaxN: the tile selection
@@ -151,11 +152,9 @@ struct Workspace {
 // Graphs kept per workspace: the lanes-per-child candidates of one run shape.
 constexpr size_t kGraphCache = 4;
 // Runs of at least this many chunks measure the lanes-per-child candidates
-// at their start: a graph of kLanesProbe children launches per candidate,
-// replayed once untimed and kLanesRounds times timed.
+// on their first kLanesRounds * candidates generations.
 constexpr uint32_t kExploreMinChunks = 4;
-constexpr uint32_t kLanesProbe = 16;
-constexpr uint32_t kLanesRounds = 4;
+constexpr uint32_t kLanesRounds = 8;
 
 static hipError_t drop_graphs(Workspace* w) {
   hipError_t e = hipSuccess;
@@ -633,84 +632,83 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
              "hipMemsetAsync(selection)");
     }
   }
+  uint32_t probed = 0;      // generations made by the lanes measurement
+  bool ended = false;       // the run ended inside them
   if (explore) {
-    // Each candidate's children launch of generation 1, kLanesProbe times in
-    // one captured graph: one untimed replay each, then kLanesRounds timed
-    // rounds in the order c1 .. ck, ck .. c1, c1 .. ck, ...; each candidate
-    // counts its fastest replay (interference only adds time).  Every
-    // launch makes generation 1 from generation 0 the same way (with
-    // elitism the timed launches list no candidates), and the first chunk
-    // makes it again, so the run's generations do not depend on the
-    // measurement; unlike timing whole chunks, every candidate is timed on
-    // the same work (the selection launches of later generations change
-    // cost as the population converges).  A selecting mode first makes
-    // generation 1's selection, which the first chunk also makes again.
-    if (!d.ew) {
-      const uint32_t cnt = select_count(cfg);
-      if (table)
-        GA_TRY(launch_perm_table(d, D, chunk, w->perm, w->capture, d.psel != nullptr),
-               "slot table kernel");
-      if (d.psel) {
-        GA_TRY(launch_paper_select(d, 0, d.psel, w->capture), "selection kernels");
-      } else if (cnt > 0) {
-        GA_TRY(launch_select(d, cnt, w->sel, 0, table ? w->perm : nullptr, w->capture),
-               "selection kernels");
-      }
-    }
-    struct ProbeGraphs {
-      std::vector<hipGraphExec_t> g;
-      ~ProbeGraphs() {
-        for (hipGraphExec_t e : g)
-          if (e) (void)hipGraphExecDestroy(e);
-      }
-    } probes;
+    // The run's first generations, launched one by one from the stream,
+    // each with the next candidate (rounds in the order c1 .. ck, ck .. c1,
+    // c1 .. ck, ...), every children launch between two events.  Every
+    // variant makes the same generations, so the run's results do not depend
+    // on the measurement; each candidate is timed on fresh generations (their
+    // inputs written by the launch before, as in the chunks) next to the
+    // others, so the cost's drift over the run (the selection's changes as
+    // the population converges) weighs on all alike.  Each candidate counts
+    // the median of its launches after the first round.
     const uint32_t nc = (uint32_t)cands.size();
-    for (uint32_t ci = 0; ci < nc; ++ci) {
+    const uint32_t K = kLanesRounds * nc;
+    while (w->ev_probe.size() < 2 * (size_t)K) {
+      hipEvent_t e;
+      GA_TRY(hipEventCreate(&e), "hipEventCreate");
+      w->ev_probe.push_back(e);
+    }
+    const uint32_t cnt = select_count(cfg);
+    if (table)
+      GA_TRY(launch_perm_table(d, D, K, w->perm, w->capture, d.psel != nullptr),
+             "slot table kernel");
+    std::vector<uint32_t> who(K);
+    for (uint32_t node = 0; node < K; ++node) {
+      const uint32_t round = node / nc, pos = node % nc;
+      const uint32_t ci = (round & 1u) ? nc - 1 - pos : pos;
+      who[node] = ci;
       PopDesc dc = d;
       set_lanes(&dc, cands[ci]);
-      dc.ecount = nullptr;  // the timed launches list no candidates
-      hipGraph_t g;
-      GA_TRY(hipStreamBeginCapture(w->capture, hipStreamCaptureModeThreadLocal),
-             "hipStreamBeginCapture");
-      ga_status cs = GA_OK;
-      for (uint32_t r = 0; r < kLanesProbe && cs == GA_OK; ++r)
-        cs = hip_status(launch_children_one(dc, 0, w->capture), "children kernel");
-      hipError_t ce = hipStreamEndCapture(w->capture, &g);
-      if (cs != GA_OK) return cs;
-      GA_TRY(ce, "hipStreamEndCapture");
-      hipGraphExec_t exec = nullptr;
-      const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      GA_TRY(ie, "hipGraphInstantiate");
-      probes.g.push_back(exec);
+      if (dc.psel) {
+        GA_TRY(launch_paper_select(dc, node, dc.psel, w->capture), "selection kernels");
+      } else if (!dc.ew && cnt > 0) {
+        GA_TRY(launch_select(dc, cnt, w->sel, node, table ? w->perm + (size_t)node * D : nullptr,
+                             w->capture),
+               "selection kernels");
+      }
+      GA_TRY(hipEventRecord(w->ev_probe[2 * node], w->capture), "hipEventRecord");
+      GA_TRY(launch_children_one(dc, node, w->capture), "children kernel");
+      GA_TRY(hipEventRecord(w->ev_probe[2 * node + 1], w->capture), "hipEventRecord");
+      if (dc.ew) GA_TRY(launch_elite_select(dc, node + 1, w->capture), "elite selection kernel");
     }
-    for (uint32_t ci = 0; ci < nc; ++ci)
-      GA_TRY(hipGraphLaunch(probes.g[ci], w->capture), "hipGraphLaunch");
-    std::vector<float> fastest(nc, 0.f);
-    for (uint32_t k = 0; k < kLanesRounds * nc; ++k) {
-      const uint32_t round = k / nc, pos = k % nc;
-      const uint32_t ci = (round & 1u) ? nc - 1 - pos : pos;
-      GA_TRY(hipEventRecord(w->ev_t[0], w->capture), "hipEventRecord");
-      GA_TRY(hipGraphLaunch(probes.g[ci], w->capture), "hipGraphLaunch");
-      GA_TRY(hipEventRecord(w->ev_t[1], w->capture), "hipEventRecord");
-      GA_TRY(hipEventSynchronize(w->ev_t[1]), "hipEventSynchronize");
-      float ms = 0;
-      GA_TRY(hipEventElapsedTime(&ms, w->ev_t[0], w->ev_t[1]), "hipEventElapsedTime");
-      if (round == 0 || ms < fastest[ci]) fastest[ci] = ms;
-    }
-    uint32_t best = 0;
-    for (uint32_t ci = 1; ci < nc; ++ci)
-      if (fastest[ci] < fastest[best]) best = ci;
-    // launches of a run that is already over (a solution in generation 0
-    // with stop-on-found) return at once: nothing was measured
+    GA_TRY(launch_advance_one(w->state, K, w->capture), "advance kernel");
     GA_TRY(hipMemcpyAsync(&w->host_state[0], w->state, sizeof(RunState), hipMemcpyDeviceToHost,
                           w->capture),
            "hipMemcpyAsync(state)");
     GA_TRY(hipStreamSynchronize(w->capture), "hipStreamSynchronize");
-    if (!run_done(w->host_state[0], 1, stop_on_found)) tuned_store(tkey, cands[best]);
+    std::vector<std::vector<float>> ms(nc);
+    for (uint32_t node = nc; node < K; ++node) {
+      float t = 0;
+      GA_TRY(hipEventElapsedTime(&t, w->ev_probe[2 * node], w->ev_probe[2 * node + 1]),
+             "hipEventElapsedTime");
+      ms[who[node]].push_back(t);
+    }
+    uint32_t best = 0;
+    float best_t = 0;
+    for (uint32_t ci = 0; ci < nc; ++ci) {
+      std::vector<float>& v = ms[ci];
+      std::sort(v.begin(), v.end());
+      const float med = v[v.size() / 2];
+      if (ci == 0 || med < best_t) {
+        best = ci;
+        best_t = med;
+      }
+    }
+    probed = K;
+    // a run that ended inside the measured generations (launches after its
+    // end return at once) measured nothing
+    ended = run_done(w->host_state[0], cfg->max_generations, stop_on_found);
+    if (!ended) tuned_store(tkey, cands[best]);
     set_lanes(&d, cands[best]);
   }
-  if (nchunks > 0) {
+  // chunks for the generations after the measured ones
+  const uint32_t rest = ended || probed >= cfg->max_generations
+                            ? 0u
+                            : (uint32_t)(((uint64_t)cfg->max_generations - probed + chunk - 1) / chunk);
+  if (rest > 0) {
     st = capture(d);
     if (st != GA_OK) return st;
     // the capture stream starts after the work already enqueued on s
@@ -727,8 +725,8 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     };
     st = launch_chunk(0);
     if (st != GA_OK) return st;
-    for (uint32_t k = 0; k < nchunks; ++k) {
-      if (k + 1 < nchunks) {
+    for (uint32_t k = 0; k < rest; ++k) {
+      if (k + 1 < rest) {
         st = launch_chunk(k + 1);
         if (st != GA_OK) return st;
       }
@@ -749,7 +747,7 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
       uint32_t made = std::min(cfg->max_generations, hs.gen_base);
       if (stop_on_found && hs.found_gen < made) made = hs.found_gen;
       g_timing.total_ms += ms;
-      g_timing.gens += made;
+      g_timing.gens += made > probed ? made - probed : 0;
     }
   }
   if (nchunks > 0) {

@@ -544,19 +544,21 @@ def test_run_paper_study_cells(m, nc, nr, kind, gens):
     ga.Config(m=40, n=400, seed=32, elite=5, fitness=ga.FIT_ABS, max_generations=300, flags=0),
     ga.Config(m=20, n=1500, seed=33, max_generations=700, flags=0),
     ga.Config(m=40, n=400, seed=34, elite=5, fitness=ga.FIT_ABS, max_generations=450, flags=0),
-    # paper mode: generation 1's selection made before the measurement and again by the run
+    # paper mode: the measured generations select and read the slot table as the chunks do
     ga.Config(m=16, n=2000, seed=35, selection=ga.SEL_PAPER, fitness=ga.FIT_F1,
               xo_threshold=1 << 32, mut_threshold=1 << 32, nc=2, nr=2, max_generations=650,
               flags=0),
-    # a solution found in the first chunk, after the measurement
+    # m = 8 runs find a solution in about 14 generations: inside the measured ones
     ga.Config(m=8, n=1024, seed=36, max_generations=700),
+    ga.Config(m=8, n=1024, seed=38, max_generations=700),
     # the shortest run that measures (four chunks)
     ga.Config(m=12, n=600, seed=37, elite=3, fitness=ga.FIT_NNZ, max_generations=193, flags=0),
 ])
 def test_run_tunes_lanes_inside_the_run(cfg):
     """A run long enough to time every lanes-per-child variant on its own
-    generation 1 before its chunks, then one that reuses the measured choice:
-    both equal the oracle's run, and the choice is one of the variants."""
+    first generations (launched one by one, the variants in turn), then one
+    that reuses the measured choice: both equal the oracle's run, and the
+    choice is one of the variants."""
     torch_cuda()
     announce("run tuned twice", cfg)
     _same_run(cfg)
