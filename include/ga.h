@@ -93,9 +93,11 @@ enum {
    * child q draws its own (index q, the third method).                     */
   GA_MUT_SHARED = 2u,
   /* Lanes per child in the children kernel (the tile shape), bits 8..12 of
-   * flags: 0 lets the library's tuning table choose; 2, 4, 8 or 16 force it
-   * (orders 36..64: 4 or 8; orders 68..128: 8 or 16).  Results do not
-   * depend on it.                                                          */
+   * flags: 0 lets the library choose (ga_run of at least 193 generations
+   * times the candidates on its own first generations, launched one by one,
+   * and remembers the choice per run shape; otherwise the tuning table);
+   * 2, 4, 8 or 16 force it (orders 36..64: 4 or 8; orders 68..128: 8 or
+   * 16).  Results do not depend on it.                                     */
   GA_LANES_SHIFT = 8u,
   GA_LANES_MASK = 0x1F00u,
   /* How ga_fitness and ga_fitness_repeat form the Gram products (Sec. 3.2),
@@ -314,7 +316,8 @@ ga_status ga_check_invariants(const ga_config* cfg, const uint32_t* pop,
 /*
  * Timing, for measurement.  While enabled, ga_run records HIP events on its
  * stream around its generation loop (the chunks of children launches, one
- * launch per generation).  ga_timing_read returns the mean time per
+ * launch per generation; not the generations a lanes measurement makes one
+ * by one before the chunks).  ga_timing_read returns the mean time per
  * generation in milliseconds and the number of generations timed since the
  * last ga_timing_enable(1).  Not thread-safe; meant for benchmarks.
  */

@@ -1,5 +1,6 @@
-// ga_elite.hip -- elitism inside ga_run: the next generation's elites from
-// short candidate lists instead of the whole population.
+// ga_elite.hip -- elitism in ga_run, batched and served runs: the next
+// generation's elites from short candidate lists instead of the whole
+// population.
 //
 // Generation G's elites are the e smallest (key, slot) of generation G - 1,
 // stored unchanged in slots 0 .. e-1 of G, so every elite precedes every
@@ -9,11 +10,12 @@
 // of G appends those children, as (slot, key), to kEliteLists lists.  One
 // block then puts them in slot order after the elites (a bitmap of the
 // listed slots and its prefix counts give each its rank), finds the
-// threshold key T of the e-th smallest item by a two-level radix select on
-// 12-bit digits (keys are below 2^24), takes the items below T and the
-// first items equal to T in slot order, and writes their slots in
-// increasing order: the sources of the next elites, with T as the next
-// kstar.  The first generation's elites come from every individual, chosen
+// threshold key T of the e-th smallest item (every item is at most kstar:
+// one histogram of the 4096 keys up to kstar, or, when T lies below them, a
+// two-level radix select on 12-bit digits of keys below 2^24), takes the
+// items below T and the first items equal to T in slot order, and writes
+// their slots in increasing order: the sources of the next elites, with T
+// as the next kstar.  The first generation's elites come from every individual, chosen
 // by the multi-block selection of ga_select.hip.
 #include <hip/hip_runtime.h>
 

@@ -14,9 +14,13 @@ minutes of CPU each), so their results are stored here:
   result, best matrix and final-population digests;
 * ``served_slice.json``: the first requests of the served stream whose order
   is at most 16 (the others need hours of oracle time): result and best
-  matrix of each.
+  matrix of each;
+* ``paper_table2_m20.json``: the paper-mode runs of the Sec. 4.2 timing
+  configuration at order 20 (40,000 matrices, crossover and mutation on every
+  offspring, NC = 4, NR = 2, 10^4 generations, no stop on found, seed 9020),
+  keys F1 and F2: result and final-population digests of each.
 
-Usage: python tests/golden/make_golden.py {elite,batched,served} [...]
+Usage: python tests/golden/make_golden.py {elite,batched,served,table2} [...]
 """
 from __future__ import annotations
 
@@ -90,7 +94,15 @@ def served() -> None:
                                 "max_order": SERVED_MAX_ORDER, "runs": runs})
 
 
+def table2() -> None:
+    runs = [run_record(dict(m=20, n=40_000, seed=9020, fitness=kind, selection=gao.SEL_PAPER,
+                            xo_threshold=1 << 32, mut_threshold=1 << 32, nc=4, nr=2,
+                            max_generations=10_000, stop_on_found=False), True)
+            for kind in (gao.FIT_F1, gao.FIT_F2)]
+    write("paper_table2_m20.json", {"source": "oracle gao.run", "runs": runs})
+
+
 if __name__ == "__main__":
-    jobs = {"elite": elite, "batched": batched, "served": served}
+    jobs = {"elite": elite, "batched": batched, "served": served, "table2": table2}
     for name in sys.argv[1:] or list(jobs):
         jobs[name]()

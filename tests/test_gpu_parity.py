@@ -883,9 +883,10 @@ def _from_fields(f) -> ga.Config:
 def test_full_size_m20_n40000_whole_run(kind):
     """The benchmark's timed path at full size: ga_run at m = 20, n = 40,000,
     seed 1, 500 generations, no stop on found, SQ and ABS keys.  The first
-    call measures the lanes per child on its own chunks, the second reuses
-    the measured choice (as the timed benchmark steps do); both leave the
-    oracle's final population and keys and report its result."""
+    call measures the lanes per child on its own first generations, the
+    second reuses the measured choice (as the timed benchmark steps do);
+    both leave the oracle's final population and keys and report its
+    result."""
     torch_cuda()
     cfg = ga.Config(m=20, n=40000, seed=1, fitness=kind, max_generations=500, flags=0)
     announce("whole run m20 n40000", kind)
@@ -920,6 +921,27 @@ def test_full_size_m32_n200000_elite_1000_generations():
     assert (cfg.m, cfg.n, cfg.elite, cfg.max_generations) == (32, 200000, 2000, 1000)
     for call in range(2):
         announce("whole run m32 n200000 elite, 1000 generations", call)
+        res, pop, keys = _run_gpu(cfg)
+        _equals_record(res, rec)
+        assert _digest(keys.astype("<u4")) == rec["keys_sha256"], call
+        assert _digest(pop) == rec["population_sha256"], call
+
+
+@pytest.mark.parametrize("key", ["F1", "F2"])
+def test_full_size_table2_m20_paper_mode_10000_generations(key):
+    """The benchmark's paper-mode leg at full size (Sec. 4.2 timing
+    configuration at m = 20: 40,000 matrices, NC = 4, NR = 2, 10^4
+    generations, no stop on found), twice (lane measurement, then the
+    measured choice): result and digests of the final population and keys
+    equal the stored oracle run."""
+    torch_cuda()
+    runs = _golden("paper_table2_m20.json")["runs"]
+    rec = runs[0 if key == "F1" else 1]
+    cfg = _from_fields(rec["config"])
+    assert (cfg.m, cfg.n, cfg.max_generations, cfg.nc, cfg.nr) == (20, 40000, 10000, 4, 2)
+    assert cfg.fitness == (ga.FIT_F1 if key == "F1" else ga.FIT_F2)
+    for call in range(2):
+        announce("whole run table2 m20", key, call)
         res, pop, keys = _run_gpu(cfg)
         _equals_record(res, rec)
         assert _digest(keys.astype("<u4")) == rec["keys_sha256"], call
