@@ -478,6 +478,11 @@ def test_run_plain_m8_config():
     ga.Config(m=8, n=65540, seed=20, selection=ga.SEL_PAPER, fitness=ga.FIT_F1,
               xo_threshold=1 << 32, mut_threshold=1 << 32, nc=1, nr=2, max_generations=10,
               flags=0),
+    # the same, long enough for the run to measure its lanes per child on its
+    # first generations (their selections reading the slot table's rows)
+    ga.Config(m=8, n=65540, seed=21, selection=ga.SEL_PAPER, fitness=ga.FIT_F1,
+              xo_threshold=1 << 32, mut_threshold=1 << 32, nc=1, nr=2, max_generations=200,
+              flags=0),
     # the Table 2 configuration at m = 20 (40,000 matrices, F2, NC = 4, NR = 2),
     # shortened to 300 generations
     ga.Config(m=20, n=40000, seed=9020, selection=ga.SEL_PAPER, fitness=ga.FIT_F2,
