@@ -231,21 +231,6 @@ __device__ __forceinline__ uint32_t feistel_inverse(uint64_t seed, uint32_t G,
   return (L << h) | R;
 }
 
-// One forward evaluation: round r maps (L, R) to (R, L xor f_r(R)).
-__device__ __forceinline__ uint32_t feistel_forward(uint64_t seed, uint32_t G,
-                                                    uint32_t h, uint32_t x) {
-  const uint32_t mask = (1u << h) - 1u;
-  uint32_t L = x >> h, R = x & mask;
-  for (int r = 0; r < 8; ++r) {
-    const U4 u = draw_block(seed, kStreamPerm, G, R, (uint32_t)r >> 2);
-    const uint32_t f = u[(uint32_t)r & 3u] & mask;
-    const uint32_t nr = L ^ f;
-    L = R;
-    R = nr;
-  }
-  return (L << h) | R;
-}
-
 __device__ uint32_t perm_inverse(uint64_t seed, uint32_t G, uint32_t D,
                                  uint32_t y) {
   const uint32_t h = feistel_half_bits(D);
@@ -267,8 +252,8 @@ __device__ uint32_t perm_inverse(uint64_t seed, uint32_t G, uint32_t D,
 // eight functions of its row in LDS (the two Philox blocks of every input
 // value: the same words the network's evaluations draw), and the walks then
 // take one table read per round instead of one Philox block.  Element
-// (row, e) gets exactly perm_inverse's value (feistel_forward's walk with
-// FWD).  The walks have uneven lengths (up to a dozen evaluations in a wave
+// (row, e) gets exactly perm_inverse's value; with FWD, the walk of the
+// forward network, whose round r maps (L, R) to (R, L xor f_r(R)).  The walks have uneven lengths (up to a dozen evaluations in a wave
 // of 64), so each wave owns a pool of its block's elements and a lane that
 // ends a walk takes the next element of the pool.
 constexpr uint32_t kPermPerBlock = 2048;  // elements of a row per block
