@@ -155,6 +155,7 @@ constexpr size_t kGraphCache = 4;
 // on their first kLanesRounds * candidates generations.
 constexpr uint32_t kExploreMinChunks = 4;
 constexpr uint32_t kLanesRounds = 8;
+constexpr float kLanesMargin = 0.03f;
 
 static hipError_t drop_graphs(Workspace* w) {
   hipError_t e = hipSuccess;
@@ -608,6 +609,7 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
   const TuneKey tkey = tune_key(cfg, d);
   const std::vector<uint32_t> cands = lanes_candidates(cfg->m);
   bool explore = false;
+  const uint32_t table_lanes = d.lanes;  // the tuning table's choice
   if (!forced_lanes(cfg)) {
     uint32_t known = 0;
     if (tuned_lookup(tkey, &known)) set_lanes(&d, known);
@@ -643,7 +645,9 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     // inputs written by the launch before, as in the chunks) next to the
     // others, so the cost's drift over the run (the selection's changes as
     // the population converges) weighs on all alike.  Each candidate counts
-    // the median of its launches after the first round.
+    // the median of its launches after the first round; the tuning table's
+    // choice (timed on whole runs of the same order and size) stays unless
+    // another candidate is faster by more than kLanesMargin.
     const uint32_t nc = (uint32_t)cands.size();
     const uint32_t K = kLanesRounds * nc;
     while (w->ev_probe.size() < 2 * (size_t)K) {
@@ -688,15 +692,18 @@ ga_status ga_run(const ga_config* cfg, uint32_t* pop_a, uint32_t* pop_b,
     }
     uint32_t best = 0;
     float best_t = 0;
+    std::vector<float> med(nc);
     for (uint32_t ci = 0; ci < nc; ++ci) {
       std::vector<float>& v = ms[ci];
       std::sort(v.begin(), v.end());
-      const float med = v[v.size() / 2];
-      if (ci == 0 || med < best_t) {
+      med[ci] = v[v.size() / 2];
+      if (ci == 0 || med[ci] < best_t) {
         best = ci;
-        best_t = med;
+        best_t = med[ci];
       }
     }
+    for (uint32_t ci = 0; ci < nc; ++ci)
+      if (cands[ci] == table_lanes && best_t > (1.f - kLanesMargin) * med[ci]) best = ci;
     probed = K;
     // a run that ended inside the measured generations (launches after its
     // end return at once) measured nothing
