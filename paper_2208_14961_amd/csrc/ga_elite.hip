@@ -15,8 +15,8 @@
 // two-level radix select on 12-bit digits of keys below 2^24), takes the
 // items below T and the first items equal to T in slot order, and writes
 // their slots in increasing order: the sources of the next elites, with T
-// as the next kstar.  The first generation's elites come from every individual, chosen
-// by the multi-block selection of ga_select.hip.
+// as the next kstar.  The first generation's elites come from every
+// individual, chosen by the multi-block selection of ga_select.hip.
 #include <hip/hip_runtime.h>
 
 #include "ga_common.h"
